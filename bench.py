@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Throughput of Z_p-RAID encode and two-erasure recovery on one MI355X.
+
+Workload: p = 13, k = 12 data strips, rows of 4 KiB (48 KiB strips), 4096
+stripes = 2.25 GiB of user data, uniform random bytes from the seeded
+generators, resident in HBM before timing starts.  One step is the whole
+hot path over that batch: one encode launch (P and Q of every stripe) and one
+recovery launch in which every stripe rebuilds a pair of strips drawn
+uniformly from its 91 pairs (two data strips, data + P, data + Q, or P + Q).
+`value` is user bytes made whole per second: 2 x 2.25 GiB per step.
+
+Also reported: per-kernel HIP-event timing and latency percentiles, the
+roofline of the dominant kernel (HBM bound), the GF(256) Reed-Solomon P+Q
+kernel on the same bytes, recovery throughput at p = 29, k = 28, 1 KiB rows,
+8192 stripes, and the CPU oracle timed on a bounded sample of the workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "encode & 2-erasure recovery GB/s user data; % HBM peak; p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+SEED = 2
+P, K, W, NSTRIPES = 13, 12, 4096, 4096
+KERNEL_SOURCES = ["paper_cs_0611109_amd/csrc/zp_core.hpp", "paper_cs_0611109_amd/csrc/zp_kernels.hip",
+                  "paper_cs_0611109_amd/csrc/raid6c_internal.h"]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pct(vals, q):
+    s = sorted(vals)
+    if not s:
+        return None
+    i = min(len(s) - 1, max(0, int(round(q / 100.0 * (len(s) - 1)))))
+    return s[i]
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def lookup_traffic(kernel: str, cfg, bytes_per_launch: int):
+    """Measured HBM bytes per launch of `kernel` from the committed counter
+    summary, when it was taken on the current kernel source and launch
+    configuration; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    e = table.get(kernel)
+    if not e or e.get("source_sha256") != source_digest() or tuple(e.get("config", ())) != tuple(cfg):
+        return None
+    if e.get("algorithmic_bytes") != bytes_per_launch:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def fill_batch(batch, seed, chunk=256):
+    import numpy as np
+    import torch
+
+    import datagen
+    p, k, w, n = batch.p, batch.k, batch.row_bytes, batch.nstripes
+    host = torch.empty((chunk, k, p - 1, w), dtype=torch.uint8).pin_memory()
+    for s0 in range(0, n, chunk):
+        c = min(chunk, n - s0)
+        datagen.fill_stripes(seed, s0, c, k, p, w, out=host.numpy()[:c])
+        batch.tensor[s0:s0 + c, :k].copy_(host[:c], non_blocking=False)
+    del np
+
+
+def time_launches(fn, reps, stream):
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def cpu_baseline(batch, er_host, seconds: float):
+    """The CPU oracle (untuned, NumPy, one thread) on successive stripes of the
+    same workload for about `seconds`; also checks the GPU results on them."""
+    import numpy as np
+
+    import datagen
+    from oracle import zp_raid as zp
+    p, k, w = batch.p, batch.k, batch.row_bytes
+    user = k * (p - 1) * w
+    done, spent, verified = 0, 0.0, True
+    while spent < seconds and done < batch.nstripes:
+        data = datagen.stripe_data(SEED, done, k, p, w)
+        e = tuple(int(v) for v in er_host[done])
+        t0 = time.perf_counter()
+        stripe = zp.encode_stripe(data, p)
+        bad = stripe.copy()
+        bad[list(e)] = 0
+        rec = zp.recover(bad, p, e)
+        spent += time.perf_counter() - t0
+        got = batch.tensor[done].cpu().numpy()
+        verified &= bool(np.array_equal(rec, stripe) and np.array_equal(got, stripe))
+        done += 1
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {
+        "value": round(2 * user * done / spent / 1e9, 6),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {done} stripes of the workload, encode + recovery of each stripe's pair, "
+                  f"NumPy oracle on one thread, {spent:.1f} s",
+        "host_cpus": len(os.sched_getaffinity(0)),
+        "cpu_model": cpu_model,
+        "gpu_results_match_oracle_on_sample": verified,
+    }
+
+
+def extras(reps, stream):
+    """Comparison and second-geometry measurements (not part of `value`)."""
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    out = {}
+
+    # GF(256) Reed-Solomon P+Q on the bytes of the main workload's geometry.
+    b = r.StripeBatch.empty(P, K, W, NSTRIPES)
+    b.tensor[:, :K].random_(0, 256)
+    ms = time_launches(lambda: b.rs_encode(), reps, stream)
+    mean = sum(ms) / len(ms)
+    out["rs_gf256_encode"] = {
+        "GBps_user": round(b.user_bytes / (mean / 1e3) / 1e9, 1),
+        "hbm_frac": round((K + 2) * b.strip_stride * NSTRIPES / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "ms_p50": round(pct(ms, 50), 4), "ms_p99": round(pct(ms, 99), 4),
+    }
+    zp_ms = time_launches(lambda: b.encode(), reps, stream)
+    out["zp_encode_same_bytes_ms_p50"] = round(pct(zp_ms, 50), 4)
+    del b
+    torch.cuda.empty_cache()
+
+    # Recovery at p = 29, k = 28, 1 KiB rows, 8192 stripes.
+    p3, k3, w3, n3 = 29, 28, 1024, 8192
+    b = r.StripeBatch.empty(p3, k3, w3, n3)
+    b.tensor[:, :k3].random_(0, 256)
+    b.encode()
+    res = {}
+    for kind in ("dd", "dp", "dq"):
+        er = torch.from_numpy(datagen.erasures(3, n3, k3, kind)).to("cuda:0")
+        ms = time_launches(lambda: b.recover(er), reps, stream)
+        mean = sum(ms) / len(ms)
+        res[kind] = {
+            "GBps_user": round(b.user_bytes / (mean / 1e3) / 1e9, 1),
+            "hbm_frac": round((k3 + 2) * b.strip_stride * n3 / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "ms_p50": round(pct(ms, 50), 4), "ms_p99": round(pct(ms, 99), 4),
+        }
+    ms = time_launches(lambda: b.encode(), reps, stream)
+    mean = sum(ms) / len(ms)
+    res["encode"] = {"GBps_user": round(b.user_bytes / (mean / 1e3) / 1e9, 1),
+                     "hbm_frac": round((k3 + 2) * b.strip_stride * n3 / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    out["p29_k28_w1024_x8192"] = res
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (stripes are independent, "
+              "so more GPUs would shard stripes with no communication; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    r.load()
+    stream = torch.cuda.current_stream()
+
+    log(f"allocating and filling p={P} k={K} W={W} x {NSTRIPES} stripes")
+    batch = r.StripeBatch.empty(P, K, W, NSTRIPES)
+    fill_batch(batch, SEED)
+    er_host = datagen.erasures(SEED, NSTRIPES, K, "any")
+    er = torch.from_numpy(er_host).to("cuda:0")
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        batch.encode()
+        if ev is not None:
+            ev[1].record(stream)
+        batch.recover(er, bad)
+        if ev is not None:
+            ev[2].record(stream)
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if int(bad.item()) != 0:
+        raise RuntimeError("recovery rejected erasure entries")
+    enc_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    rec_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    user = batch.user_bytes
+    alg_bytes = (K + 2) * batch.strip_stride * NSTRIPES           # per launch, encode and recovery alike
+    enc_mean = sum(enc_ms) / len(enc_ms)
+    rec_mean = sum(rec_ms) / len(rec_ms)
+    value = 2 * user / (ms_per_step / 1e3) / 1e9
+
+    dom = "recover" if rec_mean >= enc_mean else "encode"
+    dom_ms = rec_mean if dom == "recover" else enc_mean
+    vec, threads = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
+    kname = f"zp_{dom}_kernel<{P},{vec}>"
+    achieved = alg_bytes / (dom_ms / 1e3) / 1e9
+    traffic = lookup_traffic(kname, (vec, threads), alg_bytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": kname, "launch": {"vec": vec, "threads": threads},
+                "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(dom_ms, 4)}
+    log(f"value {value:.1f} GB/s; encode {enc_mean:.3f} ms, recovery {rec_mean:.3f} ms per launch")
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded uniform random bytes)",
+        "config": {"workload": "Z_p-RAID encode + two-erasure recovery, p=13 k=12 W=4096 B x 4096 stripes",
+                   "p": P, "k": K, "row_bytes": W, "nstripes": NSTRIPES,
+                   "user_bytes_per_pass": user, "passes_per_step": 2,
+                   "erasures": "per-stripe pair uniform over all 91 strip pairs", "parallelism": "single GPU"},
+        "encode": {"GBps_user": round(user / (enc_mean / 1e3) / 1e9, 1),
+                   "hbm_frac": round(alg_bytes / (enc_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                   "ms_p50": round(pct(enc_ms, 50), 4), "ms_p99": round(pct(enc_ms, 99), 4),
+                   "launch": dict(zip(("vec", "threads"), r.raid6c_tune_get(P, 0, W)))},
+        "recover_2": {"GBps_user": round(user / (rec_mean / 1e3) / 1e9, 1),
+                      "hbm_frac": round(alg_bytes / (rec_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                      "ms_p50": round(pct(rec_ms, 50), 4), "ms_p99": round(pct(rec_ms, 99), 4),
+                      "launch": dict(zip(("vec", "threads"), r.raid6c_tune_get(P, 1, W)))},
+        "roofline": roofline,
+    }
+    if not args.no_extras:
+        log("extras: GF(256) RS comparison and p=29 recovery")
+        result["extras"] = extras(max(10, args.steps // 2), stream)
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle for about {args.cpu_seconds:.0f} s")
+        result["cpu_baseline"] = cpu_baseline(batch, er_host, args.cpu_seconds)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * raid6c.h -- cyclic-group RAID-6 (Z_p-RAID) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libraid6c.so.  The code is the one of Jackson, Rumynin and
+ * Zaboronski, "An approach to RAID-6 based on cyclic groups":
+ *
+ *   P = D_0 + D_1 + ... + D_{k-1}
+ *   Q = D_0 + g D_1 + ... + g^{k-1} D_{k-1}
+ *
+ * in the ring R_p = F2[x]/(1 + x + ... + x^{p-1}), g = x acting as the
+ * Sylvester matrix S_p (Corollary 3.2.4 with Lemma 3.4.1), p an odd prime,
+ * 1 <= k <= p data strips.  Any one or two strips of a stripe can be rebuilt
+ * from the others (Lemma 3.1.2).
+ *
+ * Layout.  A strip is p-1 rows of row_bytes bytes, row r at byte offset
+ * r*row_bytes; bit b of byte j of row r is the coefficient of x^r of lane
+ * (j, b), so every lane is an independent ring element.  A stripe is k data
+ * strips (indices 0..k-1), then P (index k), then Q (index k+1).
+ *
+ * Conventions for every entry point below:
+ *  - All buffers are device memory owned by the caller; the library never
+ *    keeps a pointer after the call returns (plans excepted, see there).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    is complete when the stream is; the calls do not synchronise.
+ *  - row_bytes must be a positive multiple of 16 and every strip pointer
+ *    16-byte aligned (the kernels move 16-, 8- or 4-byte vectors).
+ *  - Strips of one stripe must not overlap; different stripes must not
+ *    overlap in the strips a call writes.
+ *  - Arguments are checked before any device work: on an error nothing is
+ *    enqueued and nothing is written.  Return values: RAID6C_OK (0) or a
+ *    negative RAID6C_E_* code; raid6c_last_error() gives a message.
+ *  - Arithmetic is exact (XOR only); results are bit-exact.
+ *  - The calls are reentrant; they keep no state between calls.
+ */
+#ifndef RAID6C_H
+#define RAID6C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAID6C_OK              0
+#define RAID6C_E_ARG          (-1) /* invalid argument (bad p, k, index, size, alignment) */
+#define RAID6C_E_UNSUPPORTED  (-2) /* valid for the code but not built into the GPU path (p too large) */
+#define RAID6C_E_HIP          (-3) /* HIP runtime or launch failure */
+#define RAID6C_E_NOMEM        (-4) /* device or host allocation failed (plans, servers) */
+#define RAID6C_E_STATE        (-5) /* call not valid in the object's current state */
+
+/* Largest prime p the GPU kernels are built for; every odd prime up to it is
+ * supported.  Primes above it return RAID6C_E_UNSUPPORTED. */
+int raid6c_max_prime(void);
+
+/* 1 when p is an odd prime <= raid6c_max_prime(), else 0. */
+int raid6c_is_supported_prime(int p);
+
+/* Static text for a RAID6C_* code. */
+const char* raid6c_strerror(int code);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* raid6c_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Single stripe
+ * ------------------------------------------------------------------------ */
+
+/* Encode one stripe: P = sum_t D_t, Q = sum_t g^t D_t (Corollary 3.2.4; the
+ * 0-based indexing of the Reed-Solomon parity of Section 4.1).
+ *   data : host array of k device pointers, data[t] = strip D_t (read only)
+ *   P, Q : device strips written with the parities
+ * Errors: RAID6C_E_ARG if p is not an odd prime, k not in [1, p], row_bytes
+ * not a positive multiple of 16, or a pointer NULL or misaligned;
+ * RAID6C_E_UNSUPPORTED if p > raid6c_max_prime(). */
+int raid6c_encode(int p, int k, size_t row_bytes, const void* const* data,
+                  void* P, void* Q, void* stream);
+
+/* Rebuild one erased strip e (0..k+1) in place from the k+1 others.
+ * Data strip: D_e = P + sum_{t != e} D_t (RAID-5 parity, Section 1); P or Q:
+ * recomputed from the data (first / second parity equation).
+ *   strips : host array of k+2 device pointers (D_0..D_{k-1}, P, Q); only
+ *            strips[e] is written, its input contents are ignored.
+ * Errors: as raid6c_encode, plus RAID6C_E_ARG if e is out of range. */
+int raid6c_recover_1(int p, int k, size_t row_bytes, void* const* strips,
+                     int e, void* stream);
+
+/* Rebuild two erased strips e0 != e1 (any order, 0..k+1) in place
+ * (Lemma 3.1.2; the two-data case as in Sections 4.3 and 4.6):
+ *   P+Q       : both recomputed from the data;
+ *   D_x + P   : D_x = g^{p-x}(Q + sum_{t != x} g^t D_t), then P;
+ *   D_x + Q   : D_x = P + sum_{t != x} D_t, then Q;
+ *   D_x + D_y : (x < y, z = y-x) dP = P + P_xy, dQ = Q + Q_xy,
+ *               D_y = (1+g^z)^{-1}(dP + g^{p-x} dQ), D_x = D_y + dP.
+ *   strips : host array of k+2 device pointers; only the two erased strips
+ *            are written, their input contents are ignored.
+ * Errors: as raid6c_recover_1, plus RAID6C_E_ARG if e0 == e1. */
+int raid6c_recover_2(int p, int k, size_t row_bytes, void* const* strips,
+                     int e0, int e1, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Many stripes of one geometry in one launch (strided layout)
+ *
+ * Strip j of stripe s starts at base + s*stripe_stride + j*strip_stride,
+ * j = 0..k+1.  Both strides are byte counts, multiples of 16, with
+ * strip_stride >= (p-1)*row_bytes and, when nstripes > 1,
+ * stripe_stride >= (k+2)*strip_stride (strips never overlap).  nstripes = 0
+ * is a valid empty call.
+ * ------------------------------------------------------------------------ */
+
+/* Encode nstripes stripes: writes the P and Q strips of each (same math as
+ * raid6c_encode).  Errors: as raid6c_encode, plus RAID6C_E_ARG for strides
+ * that are misaligned or let strips overlap. */
+int raid6c_encode_n(int p, int k, size_t row_bytes, void* base,
+                    size_t strip_stride, size_t stripe_stride, size_t nstripes,
+                    void* stream);
+
+/* Rebuild, per stripe, the one or two strips named by
+ * erasures[2s], erasures[2s+1] (device int32 array of 2*nstripes entries;
+ * erasures[2s+1] = -1 means a single erasure).  Same math as
+ * raid6c_recover_1 / raid6c_recover_2; only erased strips are written.
+ * The erasure array lives on the device, so it is checked by the kernel: a
+ * stripe whose entries are invalid (out of range, equal, or a first entry
+ * of -1) is left untouched and, when bad_count (device int32, may be NULL)
+ * is given, counted into *bad_count with an atomic add.
+ * Errors: as raid6c_encode_n, plus RAID6C_E_ARG if erasures is NULL or
+ * misaligned. */
+int raid6c_recover_n(int p, int k, size_t row_bytes, void* base,
+                     size_t strip_stride, size_t stripe_stride, size_t nstripes,
+                     const int32_t* erasures, int32_t* bad_count, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Comparison code: Reed-Solomon P+Q over GF(256), polynomial 0x11D
+ * ------------------------------------------------------------------------ */
+
+/* Encode nstripes Reed-Solomon stripes (Section 4.1):
+ * P = sum_t D_t, Q = sum_t {02}^t D_t bytewise in GF(2)[x]/(x^8+x^4+x^3+x^2+1),
+ * Q by Horner's rule with the multiply-by-{02} of Section 4.2.
+ * Each strip is strip_bytes bytes (a positive multiple of 16); strip j of
+ * stripe s starts at base + s*stripe_stride + j*strip_stride, j = 0..k-1 data,
+ * k = P, k+1 = Q.  1 <= k <= 255 (the order of {02}).
+ * Errors: RAID6C_E_ARG for k out of range, sizes, strides or alignment. */
+int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base,
+                       size_t strip_stride, size_t stripe_stride, size_t nstripes,
+                       void* stream);
+
+/* ------------------------------------------------------------------------
+ * Launch configuration (used by the autotuner and by tests)
+ *
+ * A Z_p kernel launch is configured by `vec`, the dwords each thread moves
+ * per row (1, 2 or 4), and `threads`, the work-group size (64, 128 or 256).
+ * The library keeps one process-wide table keyed by (p, op, row-size bucket),
+ * bucket = floor(log2(row_bytes)); op 0 = encode, 1 = recovery.  Entries
+ * change only speed, never results.
+ * ------------------------------------------------------------------------ */
+
+/* Bit mask of the vector widths built for prime p (bit v set for vec = v);
+ * 0 when p is not built. */
+int raid6c_vec_mask(int p);
+
+/* Record the configuration for (p, op, bucket of row_bytes).
+ * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, vec not built for p,
+ * threads not 64/128/256. */
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int threads);
+
+/* The configuration a call with these arguments would use now.
+ * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, or NULL outputs. */
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* threads);
+
+/* Forget every recorded configuration (back to the built-in rule). */
+void raid6c_tune_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAID6C_H */

@@ -1,0 +1,173 @@
+"""ctypes binding of libraid6c.so (the C ABI declared in include/raid6c.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Device buffers are passed as integers (device
+addresses) or as torch tensors, streams as ``hipStream_t`` integers or torch
+streams; ``None`` selects torch's current stream on the current device.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libraid6c.so")
+
+RAID6C_OK = 0
+RAID6C_E_ARG = -1
+RAID6C_E_UNSUPPORTED = -2
+RAID6C_E_HIP = -3
+RAID6C_E_NOMEM = -4
+RAID6C_E_STATE = -5
+
+_c_int, _c_size, _vp = ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
+_i32p = ctypes.c_void_p
+
+# name -> (restype, argtypes); mirrors include/raid6c.h.
+SIGNATURES = {
+    "raid6c_max_prime": (_c_int, []),
+    "raid6c_is_supported_prime": (_c_int, [_c_int]),
+    "raid6c_strerror": (ctypes.c_char_p, [_c_int]),
+    "raid6c_last_error": (ctypes.c_char_p, []),
+    "raid6c_encode": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _vp, _vp, _vp]),
+    "raid6c_recover_1": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _c_int, _vp]),
+    "raid6c_recover_2": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _c_int, _c_int, _vp]),
+    "raid6c_encode_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
+    "raid6c_recover_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _i32p, _i32p, _vp]),
+    "raid6c_rs_encode_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
+    "raid6c_vec_mask": (_c_int, [_c_int]),
+    "raid6c_tune_set": (_c_int, [_c_int, _c_int, _c_size, _c_int, _c_int]),
+    "raid6c_tune_get": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
+    "raid6c_tune_clear": (None, []),
+}
+
+_lib = None
+
+
+class Raid6cError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once) and declare the signatures.  Raises when the
+    library has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `python paper_cs_0611109_amd/build.py`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    raise TypeError(f"cannot take a device address of {type(x).__name__}")
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(s, int):
+        return s
+    if hasattr(s, "cuda_stream"):
+        return int(s.cuda_stream)
+    raise TypeError("stream must be None, an int handle or a torch stream")
+
+
+def _check(rc: int) -> int:
+    if rc != RAID6C_OK:
+        lib = load()
+        msg = (lib.raid6c_last_error() or b"").decode() or lib.raid6c_strerror(rc).decode()
+        raise Raid6cError(rc, msg)
+    return rc
+
+
+def _ptr_array(items):
+    arr = (_vp * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = _ptr(it)
+    return arr
+
+
+def raid6c_max_prime() -> int:
+    return load().raid6c_max_prime()
+
+
+def raid6c_is_supported_prime(p: int) -> bool:
+    return bool(load().raid6c_is_supported_prime(p))
+
+
+def raid6c_strerror(code: int) -> str:
+    return load().raid6c_strerror(code).decode()
+
+
+def raid6c_last_error() -> str:
+    return (load().raid6c_last_error() or b"").decode()
+
+
+def raid6c_encode(p, k, row_bytes, data, P, Q, stream=None):
+    """``data``: sequence of k device strips; ``P``, ``Q``: device strips."""
+    return _check(load().raid6c_encode(p, k, row_bytes, _ptr_array(list(data)), _ptr(P), _ptr(Q),
+                                       _stream(stream)))
+
+
+def raid6c_recover_1(p, k, row_bytes, strips, e, stream=None):
+    """``strips``: sequence of k+2 device strips (D_0..D_{k-1}, P, Q)."""
+    return _check(load().raid6c_recover_1(p, k, row_bytes, _ptr_array(list(strips)), e, _stream(stream)))
+
+
+def raid6c_recover_2(p, k, row_bytes, strips, e0, e1, stream=None):
+    return _check(load().raid6c_recover_2(p, k, row_bytes, _ptr_array(list(strips)), e0, e1,
+                                          _stream(stream)))
+
+
+def raid6c_encode_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, stream=None):
+    return _check(load().raid6c_encode_n(p, k, row_bytes, _ptr(base), strip_stride, stripe_stride,
+                                         nstripes, _stream(stream)))
+
+
+def raid6c_recover_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, erasures,
+                     bad_count=None, stream=None):
+    """``erasures``: device int32 array of 2*nstripes entries (second = -1 for one erasure)."""
+    return _check(load().raid6c_recover_n(p, k, row_bytes, _ptr(base), strip_stride, stripe_stride,
+                                          nstripes, _ptr(erasures), _ptr(bad_count), _stream(stream)))
+
+
+def raid6c_rs_encode_n(k, strip_bytes, base, strip_stride, stripe_stride, nstripes, stream=None):
+    return _check(load().raid6c_rs_encode_n(k, strip_bytes, _ptr(base), strip_stride, stripe_stride,
+                                            nstripes, _stream(stream)))
+
+
+def raid6c_vec_mask(p: int) -> int:
+    return load().raid6c_vec_mask(p)
+
+
+def raid6c_tune_set(p, op, row_bytes, vec, threads):
+    return _check(load().raid6c_tune_set(p, op, row_bytes, vec, threads))
+
+
+def raid6c_tune_get(p, op, row_bytes):
+    v, t = _c_int(), _c_int()
+    _check(load().raid6c_tune_get(p, op, row_bytes, ctypes.byref(v), ctypes.byref(t)))
+    return v.value, t.value
+
+
+def raid6c_tune_clear():
+    load().raid6c_tune_clear()

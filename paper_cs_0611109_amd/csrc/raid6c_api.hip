@@ -1,0 +1,317 @@
+// raid6c_api.hip -- the C ABI of libraid6c (declared in include/raid6c.h):
+// argument checks, launch configuration and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/raid6c.h"
+#include "raid6c_internal.h"
+#include "tune.h"
+
+namespace raid6c {
+
+#define RAID6C_PRIMES(X) \
+  X(3) X(5) X(7) X(11) X(13) X(17) X(19) X(23) X(29) X(31) X(37) X(41) X(43) X(47) X(53) X(59) X(61)
+
+#define RAID6C_DECL(p) const ZpPrimeEntry* zp_entry_##p();
+RAID6C_PRIMES(RAID6C_DECL)
+#undef RAID6C_DECL
+
+const ZpPrimeEntry* zp_prime_entry(int p) {
+  switch (p) {
+#define RAID6C_CASE(q) \
+  case q:              \
+    return zp_entry_##q();
+    RAID6C_PRIMES(RAID6C_CASE)
+#undef RAID6C_CASE
+    default:
+      return nullptr;
+  }
+}
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+static bool is_odd_prime(int p) {
+  if (p < 3 || (p % 2) == 0) return false;
+  for (int d = 3; d * d <= p; d += 2)
+    if (p % d == 0) return false;
+  return true;
+}
+
+static bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
+// Common checks of p, k and the row size.
+int check_geometry(int p, int k, size_t row_bytes) {
+  if (!is_odd_prime(p)) return fail(RAID6C_E_ARG, "p = %d is not an odd prime", p);
+  if (p > kMaxPrime)
+    return fail(RAID6C_E_UNSUPPORTED, "p = %d exceeds the largest built prime %d", p, kMaxPrime);
+  if (k < 1 || k > p) return fail(RAID6C_E_ARG, "k = %d must satisfy 1 <= k <= p = %d", k, p);
+  if (row_bytes == 0 || (row_bytes % 16) != 0)
+    return fail(RAID6C_E_ARG, "row_bytes = %zu must be a positive multiple of 16", row_bytes);
+  if ((size_t)(p - 1) * row_bytes >= ((size_t)1 << 31))
+    return fail(RAID6C_E_ARG, "a strip of (p-1)*row_bytes = %zu bytes must stay below 2 GiB",
+                (size_t)(p - 1) * row_bytes);
+  return RAID6C_OK;
+}
+
+static int check_strided(int p, int k, size_t row_bytes, const void* base, size_t strip_stride,
+                         size_t stripe_stride, size_t nstripes) {
+  int rc = check_geometry(p, k, row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  if (nstripes == 0) return RAID6C_OK;
+  if (base == nullptr || !aligned16(base)) return fail(RAID6C_E_ARG, "base is NULL or not 16-byte aligned");
+  const size_t strip = (size_t)(p - 1) * row_bytes;
+  if ((strip_stride % 16) != 0 || strip_stride < strip)
+    return fail(RAID6C_E_ARG, "strip_stride = %zu must be a multiple of 16 and >= (p-1)*row_bytes = %zu",
+                strip_stride, strip);
+  if (nstripes > 1 && ((stripe_stride % 16) != 0 || stripe_stride < (size_t)(k + 2) * strip_stride))
+    return fail(RAID6C_E_ARG,
+                "stripe_stride = %zu must be a multiple of 16 and >= (k+2)*strip_stride = %zu",
+                stripe_stride, (size_t)(k + 2) * strip_stride);
+  if (nstripes > 0xFFFFFFFFull) return fail(RAID6C_E_ARG, "nstripes exceeds 2^32-1");
+  return RAID6C_OK;
+}
+
+static int check_strip_ptrs(int n, const void* const* ptrs, size_t strip_bytes) {
+  if (ptrs == nullptr) return fail(RAID6C_E_ARG, "strip pointer array is NULL");
+  for (int j = 0; j < n; ++j) {
+    if (ptrs[j] == nullptr || !aligned16(ptrs[j]))
+      return fail(RAID6C_E_ARG, "strip %d is NULL or not 16-byte aligned", j);
+  }
+  for (int i = 0; i < n; ++i) {
+    const uintptr_t a0 = (uintptr_t)ptrs[i];
+    for (int j = i + 1; j < n; ++j) {
+      const uintptr_t b0 = (uintptr_t)ptrs[j];
+      if (a0 < b0 + strip_bytes && b0 < a0 + strip_bytes)
+        return fail(RAID6C_E_ARG, "strips %d and %d overlap", i, j);
+    }
+  }
+  return RAID6C_OK;
+}
+
+// Launch a Z_p kernel over `nstripes` stripes, splitting the grid when needed.
+static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream) {
+  if (nstripes == 0) return RAID6C_OK;
+  const ZpPrimeEntry* e = zp_prime_entry(p);
+  if (e == nullptr) return fail(RAID6C_E_UNSUPPORTED, "p = %d is not built", p);
+  const ZpConfig cfg = choose_config(p, kind, a.row_bytes, e->vec_mask);
+  const uint64_t tile_bytes = (uint64_t)cfg.threads * cfg.vec * 4;
+  a.tiles = (uint32_t)((a.row_bytes + tile_bytes - 1) / tile_bytes);
+  // Keep grid * threads below 2^31.
+  const uint64_t max_blocks = (((uint64_t)1 << 31) / cfg.threads);
+  const uint64_t chunk = max_blocks / a.tiles;
+  size_t done = 0;
+  while (done < nstripes) {
+    const size_t n = (nstripes - done) < chunk ? (nstripes - done) : chunk;
+    ZpArgs b = a;
+    if (done != 0) {
+      for (int j = 0; j < a.k + 2; ++j) b.strip[j] = a.strip[j] + done * a.stripe_stride;
+      if (a.erasures != nullptr) b.erasures = a.erasures + 2 * done;
+    }
+    b.nstripes = (uint32_t)n;
+    const hipError_t err = e->launch(kind, cfg, b, (uint32_t)(n * a.tiles), (hipStream_t)stream);
+    if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    done += n;
+  }
+  return RAID6C_OK;
+}
+
+static ZpArgs strided_args(int k, size_t row_bytes, void* base, size_t strip_stride, size_t stripe_stride) {
+  ZpArgs a;
+  memset(&a, 0, sizeof a);
+  for (int j = 0; j < k + 2; ++j) a.strip[j] = (uint8_t*)base + (size_t)j * strip_stride;
+  a.stripe_stride = stripe_stride;
+  a.row_bytes = row_bytes;
+  a.k = k;
+  a.e0 = -1;
+  a.e1 = -1;
+  return a;
+}
+
+}  // namespace raid6c
+
+using namespace raid6c;
+
+extern "C" {
+
+int raid6c_max_prime(void) { return kMaxPrime; }
+
+int raid6c_is_supported_prime(int p) { return (is_odd_prime(p) && p <= kMaxPrime) ? 1 : 0; }
+
+const char* raid6c_strerror(int code) {
+  switch (code) {
+    case RAID6C_OK: return "success";
+    case RAID6C_E_ARG: return "invalid argument";
+    case RAID6C_E_UNSUPPORTED: return "unsupported by the GPU path";
+    case RAID6C_E_HIP: return "HIP runtime error";
+    case RAID6C_E_NOMEM: return "out of memory";
+    case RAID6C_E_STATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+const char* raid6c_last_error(void) { return g_last_error.c_str(); }
+
+int raid6c_encode(int p, int k, size_t row_bytes, const void* const* data, void* P, void* Q, void* stream) {
+  g_last_error.clear();
+  int rc = check_geometry(p, k, row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  if (data == nullptr) return fail(RAID6C_E_ARG, "data pointer array is NULL");
+  const void* ptrs[kMaxStrips];
+  for (int j = 0; j < k; ++j) ptrs[j] = data[j];
+  ptrs[k] = P;
+  ptrs[k + 1] = Q;
+  rc = check_strip_ptrs(k + 2, ptrs, (size_t)(p - 1) * row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  ZpArgs a;
+  memset(&a, 0, sizeof a);
+  for (int j = 0; j < k + 2; ++j) a.strip[j] = (uint8_t*)ptrs[j];
+  a.row_bytes = row_bytes;
+  a.k = k;
+  a.e0 = a.e1 = -1;
+  return launch_zp(p, KIND_ENCODE, a, 1, stream);
+}
+
+static int recover_single_stripe(int p, int k, size_t row_bytes, void* const* strips, int e0, int e1,
+                                 void* stream) {
+  g_last_error.clear();
+  int rc = check_geometry(p, k, row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  if (classify(k, e0, e1).op == OP_BAD)
+    return fail(RAID6C_E_ARG, "invalid erasures (%d, %d) for k = %d", e0, e1, k);
+  rc = check_strip_ptrs(k + 2, (const void* const*)strips, (size_t)(p - 1) * row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  ZpArgs a;
+  memset(&a, 0, sizeof a);
+  for (int j = 0; j < k + 2; ++j) a.strip[j] = (uint8_t*)strips[j];
+  a.row_bytes = row_bytes;
+  a.k = k;
+  a.e0 = e0;
+  a.e1 = e1;
+  return launch_zp(p, KIND_RECOVER, a, 1, stream);
+}
+
+int raid6c_recover_1(int p, int k, size_t row_bytes, void* const* strips, int e, void* stream) {
+  if (e < 0 || e > k + 1) {
+    g_last_error.clear();
+    return fail(RAID6C_E_ARG, "erased strip %d out of range 0..%d", e, k + 1);
+  }
+  return recover_single_stripe(p, k, row_bytes, strips, e, -1, stream);
+}
+
+int raid6c_recover_2(int p, int k, size_t row_bytes, void* const* strips, int e0, int e1, void* stream) {
+  if (e0 < 0 || e1 < 0 || e0 > k + 1 || e1 > k + 1 || e0 == e1) {
+    g_last_error.clear();
+    return fail(RAID6C_E_ARG, "erased strips (%d, %d) must be distinct and in 0..%d", e0, e1, k + 1);
+  }
+  return recover_single_stripe(p, k, row_bytes, strips, e0, e1, stream);
+}
+
+int raid6c_encode_n(int p, int k, size_t row_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                    size_t nstripes, void* stream) {
+  g_last_error.clear();
+  int rc = check_strided(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes);
+  if (rc != RAID6C_OK || nstripes == 0) return rc;
+  ZpArgs a = strided_args(k, row_bytes, base, strip_stride, stripe_stride);
+  return launch_zp(p, KIND_ENCODE, a, nstripes, stream);
+}
+
+int raid6c_recover_n(int p, int k, size_t row_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                     size_t nstripes, const int32_t* erasures, int32_t* bad_count, void* stream) {
+  g_last_error.clear();
+  int rc = check_strided(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes);
+  if (rc != RAID6C_OK) return rc;
+  if (nstripes == 0) return RAID6C_OK;
+  if (erasures == nullptr || ((uintptr_t)erasures & 3u) != 0)
+    return fail(RAID6C_E_ARG, "erasures is NULL or not 4-byte aligned");
+  if (bad_count != nullptr && ((uintptr_t)bad_count & 3u) != 0)
+    return fail(RAID6C_E_ARG, "bad_count is not 4-byte aligned");
+  ZpArgs a = strided_args(k, row_bytes, base, strip_stride, stripe_stride);
+  a.erasures = erasures;
+  a.bad_count = bad_count;
+  return launch_zp(p, KIND_RECOVER, a, nstripes, stream);
+}
+
+int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                       size_t nstripes, void* stream) {
+  g_last_error.clear();
+  if (k < 1 || k > 255) return fail(RAID6C_E_ARG, "k = %d must satisfy 1 <= k <= 255", k);
+  if (strip_bytes == 0 || (strip_bytes % 16) != 0 || strip_bytes > ((size_t)1 << 31))
+    return fail(RAID6C_E_ARG, "strip_bytes = %zu must be a positive multiple of 16 below 2 GiB", strip_bytes);
+  if (nstripes == 0) return RAID6C_OK;
+  if (base == nullptr || !aligned16(base)) return fail(RAID6C_E_ARG, "base is NULL or not 16-byte aligned");
+  if ((strip_stride % 16) != 0 || strip_stride < strip_bytes)
+    return fail(RAID6C_E_ARG, "strip_stride must be a multiple of 16 and >= strip_bytes");
+  if (nstripes > 1 && ((stripe_stride % 16) != 0 || stripe_stride < (size_t)(k + 2) * strip_stride))
+    return fail(RAID6C_E_ARG, "stripe_stride must be a multiple of 16 and >= (k+2)*strip_stride");
+  if (nstripes > 0xFFFFFFFFull) return fail(RAID6C_E_ARG, "nstripes exceeds 2^32-1");
+  const RsConfig cfg = choose_rs_config(strip_bytes);
+  RsArgs a;
+  a.strip_stride = strip_stride;
+  a.stripe_stride = stripe_stride;
+  a.strip_bytes = strip_bytes;
+  a.k = k;
+  const uint64_t tile_bytes = (uint64_t)cfg.threads * cfg.vec * 4;
+  a.tiles = (uint32_t)((strip_bytes + tile_bytes - 1) / tile_bytes);
+  const uint64_t chunk = (((uint64_t)1 << 31) / cfg.threads) / a.tiles;
+  size_t done = 0;
+  while (done < nstripes) {
+    const size_t n = (nstripes - done) < chunk ? (nstripes - done) : chunk;
+    a.base = (uint8_t*)base + done * stripe_stride;
+    a.nstripes = (uint32_t)n;
+    const hipError_t err = rs_launch(a, cfg.vec, cfg.threads, (uint32_t)(n * a.tiles), (hipStream_t)stream);
+    if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    done += n;
+  }
+  return RAID6C_OK;
+}
+
+int raid6c_vec_mask(int p) {
+  const ZpPrimeEntry* e = zp_prime_entry(p);
+  return e ? e->vec_mask : 0;
+}
+
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int threads) {
+  g_last_error.clear();
+  const ZpPrimeEntry* e = zp_prime_entry(p);
+  if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
+  if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
+  if (!(vec == 1 || vec == 2 || vec == 4) || !(e->vec_mask & vec))
+    return fail(RAID6C_E_ARG, "vec = %d is not built for p = %d", vec, p);
+  if (!(threads == 64 || threads == 128 || threads == 256))
+    return fail(RAID6C_E_ARG, "threads = %d must be 64, 128 or 256", threads);
+  if (row_bytes == 0) return fail(RAID6C_E_ARG, "row_bytes must be positive");
+  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, threads});
+  return RAID6C_OK;
+}
+
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* threads) {
+  g_last_error.clear();
+  const ZpPrimeEntry* e = zp_prime_entry(p);
+  if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
+  if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
+  if (vec == nullptr || threads == nullptr) return fail(RAID6C_E_ARG, "NULL output");
+  const ZpConfig c = choose_config(p, (ZpKind)op, row_bytes, e->vec_mask);
+  *vec = c.vec;
+  *threads = c.threads;
+  return RAID6C_OK;
+}
+
+void raid6c_tune_clear(void) { clear_tuned(); }
+
+}  // extern "C"

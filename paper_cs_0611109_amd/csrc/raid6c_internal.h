@@ -1,0 +1,99 @@
+// raid6c_internal.h -- types shared by the host API and the kernels of libraid6c.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace raid6c {
+
+// Largest prime built into the GPU path (odd primes 3..61).
+constexpr int kMaxPrime = 61;
+constexpr int kMaxStrips = kMaxPrime + 2;  // k <= p data strips + P + Q
+
+// Cases of Lemma 3.1.2 (plus the single erasures and plain encode).
+enum : int {
+  OP_PQ = 0,   // encode / P and Q erased: recompute both
+  OP_P = 1,    // P alone erased
+  OP_Q = 2,    // Q alone erased
+  OP_D = 3,    // one data strip x erased
+  OP_DP = 4,   // data x and P
+  OP_DQ = 5,   // data x and Q
+  OP_DD = 6,   // data x < y
+  OP_BAD = 7,  // invalid erasure entry
+};
+
+struct Case {
+  int op;
+  int x;
+  int y;
+};
+
+// Classify an erasure entry (e1 = -1: single).  Valid indices are 0..k+1.
+__host__ __device__ inline Case classify(int k, int e0, int e1) {
+  Case c{OP_BAD, -1, -1};
+  const int n = k + 2;
+  if (e0 < 0 || e0 >= n) return c;
+  if (e1 == -1) {
+    if (e0 < k) c = Case{OP_D, e0, -1};
+    else if (e0 == k) c = Case{OP_P, -1, -1};
+    else c = Case{OP_Q, -1, -1};
+    return c;
+  }
+  if (e1 < 0 || e1 >= n || e1 == e0) return c;
+  const int lo = e0 < e1 ? e0 : e1;
+  const int hi = e0 < e1 ? e1 : e0;
+  if (lo == k) c = Case{OP_PQ, -1, -1};
+  else if (hi == k) c = Case{OP_DP, lo, -1};
+  else if (hi == k + 1) c = Case{OP_DQ, lo, -1};
+  else c = Case{OP_DD, lo, hi};
+  return c;
+}
+
+// Kernel arguments of the Z_p kernels (passed by value).
+struct ZpArgs {
+  uint8_t* strip[kMaxStrips];  // strip j of stripe 0 (j = 0..k+1)
+  uint64_t stripe_stride;      // bytes between consecutive stripes
+  uint64_t row_bytes;          // W
+  uint32_t nstripes;
+  uint32_t tiles;              // column tiles per row
+  int32_t k;
+  int32_t e0, e1;              // uniform erasures, used when `erasures` is NULL
+  const int32_t* erasures;     // per-stripe pairs (device), or NULL
+  int32_t* bad_count;          // device counter of rejected stripes, or NULL
+};
+
+// Launch configuration of a Z_p kernel.
+struct ZpConfig {
+  int vec;      // dwords per thread and row: 1, 2 or 4
+  int threads;  // work-group size: 64, 128 or 256
+};
+
+enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
+
+// Per-prime launchers, one translation unit per prime (zp_kernels.hip).
+// Return hipSuccess or the launch error; `ok_vec` tells whether `vec` is built.
+typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a,
+                                 uint32_t grid, hipStream_t stream);
+struct ZpPrimeEntry {
+  int p;
+  ZpLauncher launch;
+  int vec_mask;  // bit v set when vec = v is instantiated (bits 1, 2, 4)
+};
+
+const ZpPrimeEntry* zp_prime_entry(int p);  // NULL when p is not built
+
+// Reed-Solomon GF(256) comparison kernel (rs_kernels.hip).
+struct RsArgs {
+  uint8_t* base;
+  uint64_t strip_stride;
+  uint64_t stripe_stride;
+  uint64_t strip_bytes;
+  uint32_t nstripes;
+  uint32_t tiles;
+  int32_t k;
+};
+hipError_t rs_launch(const RsArgs& a, int vec, int threads, uint32_t grid, hipStream_t stream);
+
+}  // namespace raid6c

@@ -1,0 +1,29 @@
+// tune.h -- launch-configuration choice for the kernels of libraid6c.
+#pragma once
+
+#include <stdint.h>
+
+#include "raid6c_internal.h"
+
+namespace raid6c {
+
+struct RsConfig {
+  int vec;
+  int threads;
+};
+
+// Configuration for a Z_p kernel: a tuned entry when one has been recorded
+// for (p, kind, row-size bucket), else the built-in rule.
+ZpConfig choose_config(int p, ZpKind kind, uint64_t row_bytes, int vec_mask);
+
+// Configuration for the GF(256) comparison kernel.
+RsConfig choose_rs_config(uint64_t strip_bytes);
+
+// Row-size bucket used by the tuning table: floor(log2(row_bytes)), 4..30.
+int row_bucket(uint64_t row_bytes);
+
+// Record / forget a tuned configuration (the autotuner's output).
+bool set_tuned(int p, ZpKind kind, int bucket, ZpConfig cfg);
+void clear_tuned();
+
+}  // namespace raid6c

@@ -1,0 +1,128 @@
+"""Host-side checks of the C ABI: every declared symbol is exported, and bad
+arguments are rejected before any device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_cs_0611109_amd as r
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "raid6c.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(raid6c_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for n in ["raid6c_encode", "raid6c_recover_1", "raid6c_recover_2", "raid6c_encode_n",
+              "raid6c_recover_n", "raid6c_rs_encode_n", "raid6c_strerror"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(r.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_cs_0611109_amd import _lib
+    missing = [n for n in declared_functions() if n not in _lib.SIGNATURES]
+    assert not missing, missing
+
+
+def test_prime_support():
+    assert r.raid6c_max_prime() >= 53
+    for p in range(0, 80):
+        odd_prime = p >= 3 and p % 2 == 1 and all(p % d for d in range(3, int(p ** 0.5) + 1, 2))
+        assert r.raid6c_is_supported_prime(p) == (odd_prime and p <= r.raid6c_max_prime())
+        assert (r.raid6c_vec_mask(p) != 0) == r.raid6c_is_supported_prime(p)
+
+
+def _err(fn, *args, code=r.RAID6C_E_ARG, **kw):
+    with pytest.raises(r.Raid6cError) as ei:
+        fn(*args, **kw)
+    assert ei.value.code == code, str(ei.value)
+    assert r.raid6c_last_error()
+
+
+FAKE = 1 << 40  # a 16-byte-aligned address that is never dereferenced
+
+
+def test_encode_n_argument_checks():
+    ok = dict(p=5, k=4, row_bytes=64, base=FAKE, strip_stride=256, stripe_stride=6 * 256, nstripes=2, stream=0)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return r.raid6c_encode_n(a["p"], a["k"], a["row_bytes"], a["base"], a["strip_stride"],
+                                 a["stripe_stride"], a["nstripes"], stream=a["stream"])
+
+    _err(call, p=9)
+    _err(call, p=2)
+    _err(call, p=67, code=r.RAID6C_E_UNSUPPORTED)
+    _err(call, k=0)
+    _err(call, k=6)
+    _err(call, row_bytes=0)
+    _err(call, row_bytes=24)
+    _err(call, base=0)
+    _err(call, base=FAKE + 8)
+    _err(call, strip_stride=255)
+    _err(call, strip_stride=240)
+    _err(call, stripe_stride=6 * 256 - 16)
+    _err(call, row_bytes=1 << 29, strip_stride=4 << 29, stripe_stride=24 << 29)   # strip >= 2 GiB
+    assert call(nstripes=0) == 0          # empty call: no device work
+
+
+def test_recover_argument_checks():
+    strips = [FAKE + i * 4096 for i in range(6)]
+    _err(r.raid6c_recover_2, 5, 4, 64, strips, 1, 1, stream=0)
+    _err(r.raid6c_recover_2, 5, 4, 64, strips, 0, 6, stream=0)
+    _err(r.raid6c_recover_2, 5, 4, 64, strips, -1, 2, stream=0)
+    _err(r.raid6c_recover_1, 5, 4, 64, strips, 6, stream=0)
+    _err(r.raid6c_recover_1, 5, 4, 64, strips, -1, stream=0)
+    overlapping = [FAKE + i * 128 for i in range(6)]          # strips are 256 bytes
+    _err(r.raid6c_recover_2, 5, 4, 64, overlapping, 0, 1, stream=0)
+    misaligned = list(strips)
+    misaligned[3] += 4
+    _err(r.raid6c_recover_1, 5, 4, 64, misaligned, 0, stream=0)
+    _err(r.raid6c_recover_n, 5, 4, 64, FAKE, 256, 1536, 4, 0, stream=0)       # NULL erasures
+    _err(r.raid6c_recover_n, 5, 4, 64, FAKE, 256, 1536, 4, FAKE + 2, stream=0)
+
+
+def test_encode_single_argument_checks():
+    data = [FAKE + i * 4096 for i in range(4)]
+    _err(r.raid6c_encode, 5, 4, 64, data, FAKE + 4 * 4096, FAKE + 4 * 4096, stream=0)   # P == Q
+    _err(r.raid6c_encode, 5, 4, 64, data, 0, FAKE + 5 * 4096, stream=0)
+    _err(r.raid6c_encode, 7, 4, 64, data[:3] + [FAKE + 2 * 4096 + 64], FAKE + 4 * 4096, FAKE + 5 * 4096,
+         stream=0)
+
+
+def test_rs_argument_checks():
+    _err(r.raid6c_rs_encode_n, 0, 64, FAKE, 64, 64 * 4, 1, stream=0)
+    _err(r.raid6c_rs_encode_n, 256, 64, FAKE, 64, 64 * 258, 1, stream=0)
+    _err(r.raid6c_rs_encode_n, 4, 40, FAKE, 48, 48 * 6, 1, stream=0)
+    _err(r.raid6c_rs_encode_n, 4, 64, FAKE, 48, 64 * 6, 1, stream=0)
+    assert r.raid6c_rs_encode_n(4, 64, FAKE, 64, 64 * 6, 0, stream=0) == 0
+
+
+def test_tuning_table():
+    r.raid6c_tune_clear()
+    v0, t0 = r.raid6c_tune_get(13, 0, 4096)
+    assert v0 in (1, 2, 4) and t0 in (64, 128, 256)
+    r.raid6c_tune_set(13, 0, 4096, 1, 64)
+    assert r.raid6c_tune_get(13, 0, 4096) == (1, 64)
+    assert r.raid6c_tune_get(13, 0, 4096 + 2048) == (1, 64)     # same power-of-two bucket
+    assert r.raid6c_tune_get(13, 1, 4096) == r.raid6c_tune_get(13, 1, 4096)
+    r.raid6c_tune_clear()
+    assert r.raid6c_tune_get(13, 0, 4096) == (v0, t0)
+    _err(r.raid6c_tune_set, 9, 0, 64, 1, 64)
+    _err(r.raid6c_tune_set, 53, 0, 64, 4, 64)     # vec 4 not built for large p
+    _err(r.raid6c_tune_set, 13, 2, 64, 1, 64)
+    _err(r.raid6c_tune_set, 13, 0, 64, 1, 96)
