@@ -257,13 +257,13 @@ def main():
 
     dom = "recover" if rec_mean >= enc_mean else "encode"
     dom_ms = rec_mean if dom == "recover" else enc_mean
-    vec, threads = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
-    kname = f"zp_{dom}_kernel<{P},{vec}>"
+    vec, unroll, threads = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
+    kname = f"zp_{dom}_kernel<{P},{vec},{unroll}>"
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
-    traffic = lookup_traffic(kname, (vec, threads), alg_bytes)
+    traffic = lookup_traffic(kname, (vec, unroll, threads), alg_bytes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": kname, "launch": {"vec": vec, "threads": threads},
+                "kernel": kname, "launch": {"vec": vec, "unroll": unroll, "threads": threads},
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(dom_ms, 4)}
     log(f"value {value:.1f} GB/s; encode {enc_mean:.3f} ms, recovery {rec_mean:.3f} ms per launch")
 
@@ -279,11 +279,11 @@ def main():
         "encode": {"GBps_user": round(user / (enc_mean / 1e3) / 1e9, 1),
                    "hbm_frac": round(alg_bytes / (enc_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                    "ms_p50": round(pct(enc_ms, 50), 4), "ms_p99": round(pct(enc_ms, 99), 4),
-                   "launch": dict(zip(("vec", "threads"), r.raid6c_tune_get(P, 0, W)))},
+                   "launch": dict(zip(("vec", "unroll", "threads"), r.raid6c_tune_get(P, 0, W)))},
         "recover_2": {"GBps_user": round(user / (rec_mean / 1e3) / 1e9, 1),
                       "hbm_frac": round(alg_bytes / (rec_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                       "ms_p50": round(pct(rec_ms, 50), 4), "ms_p99": round(pct(rec_ms, 99), 4),
-                      "launch": dict(zip(("vec", "threads"), r.raid6c_tune_get(P, 1, W)))},
+                      "launch": dict(zip(("vec", "unroll", "threads"), r.raid6c_tune_get(P, 1, W)))},
         "roofline": roofline,
     }
     if not args.no_extras:

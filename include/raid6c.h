@@ -148,7 +148,9 @@ int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base,
  * Launch configuration (used by the autotuner and by tests)
  *
  * A Z_p kernel launch is configured by `vec`, the dwords each thread moves
- * per row (1, 2 or 4), and `threads`, the work-group size (64, 128 or 256).
+ * per row (1, 2 or 4), `unroll`, the number of data strips whose loads are
+ * issued together (1, 2 or 4), and `threads`, the work-group size (64, 128
+ * or 256).  Only some (vec, unroll) pairs are built for each prime.
  * The library keeps one process-wide table keyed by (p, op, row-size bucket),
  * bucket = floor(log2(row_bytes)); op 0 = encode, 1 = recovery.  Entries
  * change only speed, never results.
@@ -158,14 +160,18 @@ int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base,
  * 0 when p is not built. */
 int raid6c_vec_mask(int p);
 
+/* Bit mask of the unroll factors built for (p, vec) (bit u for unroll = u);
+ * 0 when the pair is not built. */
+int raid6c_unroll_mask(int p, int vec);
+
 /* Record the configuration for (p, op, bucket of row_bytes).
- * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, vec not built for p,
- * threads not 64/128/256. */
-int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int threads);
+ * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, (vec, unroll) not built
+ * for p, threads not 64/128/256. */
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads);
 
 /* The configuration a call with these arguments would use now.
  * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, or NULL outputs. */
-int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* threads);
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads);
 
 /* Forget every recorded configuration (back to the built-in rule). */
 void raid6c_tune_clear(void);

@@ -28,6 +28,7 @@ from ._lib import (  # noqa: F401
     raid6c_tune_clear,
     raid6c_tune_get,
     raid6c_tune_set,
+    raid6c_unroll_mask,
     raid6c_vec_mask,
 )
 from .layout import StripeBatch  # noqa: F401

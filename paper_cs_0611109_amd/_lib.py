@@ -37,8 +37,10 @@ SIGNATURES = {
     "raid6c_recover_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _i32p, _i32p, _vp]),
     "raid6c_rs_encode_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
     "raid6c_vec_mask": (_c_int, [_c_int]),
-    "raid6c_tune_set": (_c_int, [_c_int, _c_int, _c_size, _c_int, _c_int]),
-    "raid6c_tune_get": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
+    "raid6c_unroll_mask": (_c_int, [_c_int, _c_int]),
+    "raid6c_tune_set": (_c_int, [_c_int, _c_int, _c_size, _c_int, _c_int, _c_int]),
+    "raid6c_tune_get": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
+                                 ctypes.POINTER(_c_int)]),
     "raid6c_tune_clear": (None, []),
 }
 
@@ -159,14 +161,19 @@ def raid6c_vec_mask(p: int) -> int:
     return load().raid6c_vec_mask(p)
 
 
-def raid6c_tune_set(p, op, row_bytes, vec, threads):
-    return _check(load().raid6c_tune_set(p, op, row_bytes, vec, threads))
+def raid6c_unroll_mask(p: int, vec: int) -> int:
+    return load().raid6c_unroll_mask(p, vec)
+
+
+def raid6c_tune_set(p, op, row_bytes, vec, unroll, threads):
+    return _check(load().raid6c_tune_set(p, op, row_bytes, vec, unroll, threads))
 
 
 def raid6c_tune_get(p, op, row_bytes):
-    v, t = _c_int(), _c_int()
-    _check(load().raid6c_tune_get(p, op, row_bytes, ctypes.byref(v), ctypes.byref(t)))
-    return v.value, t.value
+    """(vec, unroll, threads) a call with these arguments would use."""
+    v, u, t = _c_int(), _c_int(), _c_int()
+    _check(load().raid6c_tune_get(p, op, row_bytes, ctypes.byref(v), ctypes.byref(u), ctypes.byref(t)))
+    return v.value, u.value, t.value
 
 
 def raid6c_tune_clear():

@@ -31,12 +31,12 @@ CFLAGS = [
 SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip"]
 
 
-def _units():
+def _units(build_dir):
     units = []
     for src in SOURCES:
-        units.append((os.path.join(CSRC, src), os.path.join(BUILD, src.replace(".hip", ".o")), []))
+        units.append((os.path.join(CSRC, src), os.path.join(build_dir, src.replace(".hip", ".o")), []))
     for p in PRIMES:
-        units.append((os.path.join(CSRC, "zp_kernels.hip"), os.path.join(BUILD, f"zp_kernels_p{p}.o"),
+        units.append((os.path.join(CSRC, "zp_kernels.hip"), os.path.join(build_dir, f"zp_kernels_p{p}.o"),
                       [f"-DRAID6C_P={p}"]))
     return units
 
@@ -52,23 +52,28 @@ def _run(cmd, verbose):
         print(out, flush=True)
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every source for gfx950 and link libraid6c.so; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int | None = None, out: str = LIB, build_dir: str = BUILD,
+          defines=()) -> str:
+    """Compile every source for gfx950 and link libraid6c.so; returns its path.
+
+    ``out``, ``build_dir`` and ``defines`` (extra -D flags) allow building
+    variants elsewhere, e.g. for tuning experiments."""
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
-    units = _units()
+    units = _units(build_dir)
+    dflags = [f"-D{d}" for d in defines]
 
     def compile_one(u):
         src, obj, extra = u
-        _run([HIPCC, *CFLAGS, *extra, "-I", CSRC, "-c", src, "-o", obj], verbose)
+        _run([HIPCC, *CFLAGS, *dflags, *extra, "-I", CSRC, "-c", src, "-o", obj], verbose)
         return obj
 
     with ThreadPoolExecutor(max_workers=jobs) as pool:
         objs = list(pool.map(compile_one, units))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

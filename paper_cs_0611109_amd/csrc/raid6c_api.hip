@@ -109,7 +109,7 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
   if (nstripes == 0) return RAID6C_OK;
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_UNSUPPORTED, "p = %d is not built", p);
-  const ZpConfig cfg = choose_config(p, kind, a.row_bytes, e->vec_mask);
+  const ZpConfig cfg = choose_config(*e, kind, a.row_bytes);
   const uint64_t tile_bytes = (uint64_t)cfg.threads * cfg.vec * 4;
   a.tiles = (uint32_t)((a.row_bytes + tile_bytes - 1) / tile_bytes);
   // Keep grid * threads below 2^31.
@@ -286,28 +286,35 @@ int raid6c_vec_mask(int p) {
   return e ? e->vec_mask : 0;
 }
 
-int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int threads) {
+int raid6c_unroll_mask(int p, int vec) {
+  const ZpPrimeEntry* e = zp_prime_entry(p);
+  if (e == nullptr || !(vec == 1 || vec == 2 || vec == 4)) return 0;
+  return e->unroll_mask[vec];
+}
+
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads) {
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
   if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
-  if (!(vec == 1 || vec == 2 || vec == 4) || !(e->vec_mask & vec))
-    return fail(RAID6C_E_ARG, "vec = %d is not built for p = %d", vec, p);
+  if (!e->has(vec, unroll))
+    return fail(RAID6C_E_ARG, "(vec = %d, unroll = %d) is not built for p = %d", vec, unroll, p);
   if (!(threads == 64 || threads == 128 || threads == 256))
     return fail(RAID6C_E_ARG, "threads = %d must be 64, 128 or 256", threads);
   if (row_bytes == 0) return fail(RAID6C_E_ARG, "row_bytes must be positive");
-  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, threads});
+  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads});
   return RAID6C_OK;
 }
 
-int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* threads) {
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads) {
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
   if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
-  if (vec == nullptr || threads == nullptr) return fail(RAID6C_E_ARG, "NULL output");
-  const ZpConfig c = choose_config(p, (ZpKind)op, row_bytes, e->vec_mask);
+  if (vec == nullptr || unroll == nullptr || threads == nullptr) return fail(RAID6C_E_ARG, "NULL output");
+  const ZpConfig c = choose_config(*e, (ZpKind)op, row_bytes);
   *vec = c.vec;
+  *unroll = c.unroll;
   *threads = c.threads;
   return RAID6C_OK;
 }

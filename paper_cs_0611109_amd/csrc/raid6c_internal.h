@@ -67,19 +67,27 @@ struct ZpArgs {
 // Launch configuration of a Z_p kernel.
 struct ZpConfig {
   int vec;      // dwords per thread and row: 1, 2 or 4
+  int unroll;   // data strips whose loads are issued together: 1, 2 or 4
   int threads;  // work-group size: 64, 128 or 256
 };
 
 enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
 
 // Per-prime launchers, one translation unit per prime (zp_kernels.hip).
-// Return hipSuccess or the launch error; `ok_vec` tells whether `vec` is built.
+// Return hipSuccess or the launch error (hipErrorInvalidValue for a
+// configuration that is not built).
 typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a,
                                  uint32_t grid, hipStream_t stream);
 struct ZpPrimeEntry {
   int p;
   ZpLauncher launch;
-  int vec_mask;  // bit v set when vec = v is instantiated (bits 1, 2, 4)
+  int vec_mask;        // bit v set when vec = v is instantiated (bits 1, 2, 4)
+  int unroll_mask[5];  // per vec: bit u set when (vec, unroll = u) is instantiated
+
+  bool has(int vec, int unroll) const {
+    return (vec == 1 || vec == 2 || vec == 4) && (vec_mask & vec) &&
+           (unroll == 1 || unroll == 2 || unroll == 4) && (unroll_mask[vec] & unroll);
+  }
 };
 
 const ZpPrimeEntry* zp_prime_entry(int p);  // NULL when p is not built

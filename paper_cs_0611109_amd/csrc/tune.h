@@ -14,12 +14,15 @@ struct RsConfig {
 
 // Configuration for a Z_p kernel: a tuned entry when one has been recorded
 // for (p, kind, row-size bucket), else the built-in rule.
-ZpConfig choose_config(int p, ZpKind kind, uint64_t row_bytes, int vec_mask);
+ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes);
+
+// The built-in rule alone.
+ZpConfig default_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes);
 
 // Configuration for the GF(256) comparison kernel.
 RsConfig choose_rs_config(uint64_t strip_bytes);
 
-// Row-size bucket used by the tuning table: floor(log2(row_bytes)), 4..30.
+// Row-size bucket used by the tuning table: floor(log2(row_bytes)), 0..30.
 int row_bucket(uint64_t row_bytes);
 
 // Record / forget a tuned configuration (the autotuner's output).

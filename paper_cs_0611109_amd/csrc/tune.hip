@@ -4,14 +4,13 @@
 #include <stdlib.h>
 
 #include <atomic>
-#include <mutex>
 
 namespace raid6c {
 
 namespace {
 
 constexpr int kBuckets = 31;
-// Packed (vec << 16 | threads), 0 = no entry; index [p][kind][bucket].
+// Packed (vec << 16 | unroll << 12 | threads), 0 = no entry; [p][kind][bucket].
 std::atomic<uint32_t> g_table[kMaxPrime + 1][2][kBuckets];
 
 int env_int(const char* name) {
@@ -19,9 +18,16 @@ int env_int(const char* name) {
   return s ? atoi(s) : 0;
 }
 
-bool valid(const ZpConfig& c, int vec_mask) {
-  return (c.vec == 1 || c.vec == 2 || c.vec == 4) && (vec_mask & c.vec) &&
-         (c.threads == 64 || c.threads == 128 || c.threads == 256);
+bool valid(const ZpPrimeEntry& e, const ZpConfig& c) {
+  return e.has(c.vec, c.unroll) && (c.threads == 64 || c.threads == 128 || c.threads == 256);
+}
+
+uint32_t pack(const ZpConfig& c) {
+  return ((uint32_t)c.vec << 16) | ((uint32_t)c.unroll << 12) | (uint32_t)c.threads;
+}
+
+ZpConfig unpack(uint32_t t) {
+  return ZpConfig{(int)(t >> 16), (int)((t >> 12) & 0xF), (int)(t & 0xFFF)};
 }
 
 }  // namespace
@@ -34,9 +40,7 @@ int row_bucket(uint64_t row_bytes) {
 
 bool set_tuned(int p, ZpKind kind, int bucket, ZpConfig cfg) {
   if (p < 3 || p > kMaxPrime || bucket < 0 || bucket >= kBuckets) return false;
-  if (!(cfg.threads == 64 || cfg.threads == 128 || cfg.threads == 256)) return false;
-  if (!(cfg.vec == 1 || cfg.vec == 2 || cfg.vec == 4)) return false;
-  g_table[p][kind][bucket].store(((uint32_t)cfg.vec << 16) | (uint32_t)cfg.threads);
+  g_table[p][kind][bucket].store(pack(cfg));
   return true;
 }
 
@@ -46,27 +50,49 @@ void clear_tuned() {
       for (auto& c : b) c.store(0);
 }
 
-ZpConfig choose_config(int p, ZpKind kind, uint64_t row_bytes, int vec_mask) {
+ZpConfig default_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) {
+  (void)kind;
+  // Pick the (vec, unroll) pair that keeps the most load bytes in flight per
+  // compute unit: registers per thread ~ (2p-1)*vec accumulators + a batch of
+  // unroll*(p-1)*vec loads + ~24 for addresses and temporaries; a SIMD holds
+  // floor(512 / registers) waves, at most 8.
+  const int p = e.p;
+  ZpConfig best{0, 0, 64};
+  long best_score = -1;
+  for (int vec = 1; vec <= 4; vec *= 2) {
+    for (int unroll = 1; unroll <= 4; unroll *= 2) {
+      if (!e.has(vec, unroll)) continue;
+      const int regs = (2 * p - 1) * vec + unroll * (p - 1) * vec + 24;
+      int waves = 512 / regs;
+      if (waves > 8) waves = 8;
+      // Lanes past the end of a short row do no work: discount them.
+      const uint64_t tile = 64ull * vec * 4;
+      const double used = row_bytes >= tile ? 1.0 : (double)row_bytes / (double)tile;
+      const long score = (long)(waves * unroll * (p - 1) * vec * used * 1000.0);
+      if (score > best_score) {
+        best_score = score;
+        best = ZpConfig{vec, unroll, 64};
+      }
+    }
+  }
+  return best;
+}
+
+ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) {
   // Explicit override (used by tuning sweeps).
   static const int env_vec = env_int("RAID6C_ZP_VEC");
+  static const int env_unroll = env_int("RAID6C_ZP_UNROLL");
   static const int env_threads = env_int("RAID6C_ZP_THREADS");
-  ZpConfig c{0, 0};
   if (env_vec != 0 && env_threads != 0) {
-    c = ZpConfig{env_vec, env_threads};
-    if (valid(c, vec_mask)) return c;
+    const ZpConfig c{env_vec, env_unroll ? env_unroll : 1, env_threads};
+    if (valid(e, c)) return c;
   }
-  const uint32_t t = g_table[p][kind][row_bucket(row_bytes)].load();
+  const uint32_t t = g_table[e.p][kind][row_bucket(row_bytes)].load();
   if (t != 0) {
-    c = ZpConfig{(int)(t >> 16), (int)(t & 0xFFFF)};
-    if (valid(c, vec_mask)) return c;
+    const ZpConfig c = unpack(t);
+    if (valid(e, c)) return c;
   }
-  // Built-in rule: vector width by register budget ((2p-1)*vec dwords of
-  // accumulators), then the smallest group that spans the row, capped at 256.
-  int vec = (p <= 7) ? 4 : (p <= 23) ? 2 : 1;
-  while (!(vec_mask & vec)) vec >>= 1;
-  int threads = 64;
-  while (threads < 256 && (uint64_t)threads * vec * 4 < row_bytes) threads *= 2;
-  return ZpConfig{vec, threads};
+  return default_config(e, kind, row_bytes);
 }
 
 RsConfig choose_rs_config(uint64_t strip_bytes) {

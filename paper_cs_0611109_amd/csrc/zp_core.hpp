@@ -51,6 +51,16 @@ template <> struct vec_t<4> { typedef uint32_t type __attribute__((ext_vector_ty
 // Buffer-resource word 3 for raw (untyped, stride 0) buffers on gfx9-class GPUs.
 constexpr int kRawBufferWord3 = 0x00020000;
 
+// Cache-policy operand of the buffer loads and stores.  Every byte is read
+// or written exactly once, so both are marked non-temporal (bit 1, "nt" on
+// gfx94x/gfx950): streamed through without displacing cache lines.
+#ifndef RAID6C_LOAD_POLICY
+#define RAID6C_LOAD_POLICY 2
+#endif
+#ifndef RAID6C_STORE_POLICY
+#define RAID6C_STORE_POLICY 2
+#endif
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const uint8_t* base, uint32_t nbytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, (int)nbytes,
                                            kRawBufferWord3);
@@ -63,28 +73,28 @@ template <int V> struct bufio;
 template <> struct bufio<1> {
   typedef uint32_t T;
   static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, RAID6C_LOAD_POLICY);
   }
   static __device__ __forceinline__ void store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, RAID6C_STORE_POLICY);
   }
 };
 template <> struct bufio<2> {
   typedef vec_t<2>::type T;
   static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, RAID6C_LOAD_POLICY);
   }
   static __device__ __forceinline__ void store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, RAID6C_STORE_POLICY);
   }
 };
 template <> struct bufio<4> {
   typedef vec_t<4>::type T;
   static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, RAID6C_LOAD_POLICY);
   }
   static __device__ __forceinline__ void store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, RAID6C_STORE_POLICY);
   }
 };
 
@@ -110,29 +120,59 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t s, int r, uint64_t W, 
   bufio<sizeof(VT) / 4>::store(v, s, col, (uint32_t)r * (uint32_t)W);
 }
 
+// acc_q <- x * acc_q in C: a cyclic shift of the p rows (register renaming).
+template <int P, typename VT>
+__device__ __forceinline__ void rotate_up(VT (&aq)[P]) {
+  const VT top = aq[P - 1];
+#pragma unroll
+  for (int u = P - 1; u > 0; --u) aq[u] = aq[u - 1];
+  aq[0] = top;
+}
+
 // Streaming phase over the data strips, skipping strips x and y (-1 = none).
-// HP: accumulate acc_p; HQ: accumulate acc_q (Horner in C).
-template <int P, int V, bool HP, bool HQ>
+// HP: accumulate acc_p; HQ: accumulate acc_q (Horner in C).  The strips are
+// taken U at a time: the U*(p-1) row loads of a batch are all issued before
+// the first of them is used, so each thread keeps U*(p-1) loads in flight.
+template <int P, int V, int U, bool HP, bool HQ>
 __device__ __forceinline__ void stream_data(const Cols& c, int k, int x, int y,
                                             typename vec_t<V>::type (&ap)[P - 1],
                                             typename vec_t<V>::type (&aq)[P]) {
   typedef typename vec_t<V>::type VT;
   constexpr int R = P - 1;
   const uint64_t W = c.a->row_bytes;
-  for (int t = k - 1; t >= 0; --t) {
-    if (HQ) {
-      // acc_q <- x * acc_q in C: cyclic shift of the p rows.
-      VT top = aq[P - 1];
+  int t = k - 1;
+  for (; t >= U - 1; t -= U) {
+    VT v[U][R];
 #pragma unroll
-      for (int u = P - 1; u > 0; --u) aq[u] = aq[u - 1];
-      aq[0] = top;
+    for (int u = 0; u < U; ++u) {
+      const int tt = t - u;
+      if (tt == x || tt == y) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = (VT)(0u);
+      } else {
+        const __amdgpu_buffer_rsrc_t b = c.strip(tt);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = ld<VT>(b, r, W, c.col);
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (HQ) rotate_up<P>(aq);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (HP) ap[r] ^= v[u][r];
+        if (HQ) aq[r] ^= v[u][r];
+      }
+    }
+  }
+  for (; t >= 0; --t) {
+    if (HQ) rotate_up<P>(aq);
     if (t == x || t == y) continue;
     const __amdgpu_buffer_rsrc_t b = c.strip(t);
     VT v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = ld<VT>(b, r, W, c.col);
-    // Keep all p-1 row loads of the strip in flight before the first use.
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -149,6 +189,7 @@ __device__ __forceinline__ void load_into(const Cols& c, int j, typename vec_t<V
   const uint64_t W = c.a->row_bytes;
 #pragma unroll
   for (int r = 0; r < P - 1; ++r) acc[r] = ld<VT>(b, r, W, c.col);
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int P, int V>
@@ -156,8 +197,13 @@ __device__ __forceinline__ void xor_from(const Cols& c, int j, typename vec_t<V>
   typedef typename vec_t<V>::type VT;
   const __amdgpu_buffer_rsrc_t b = c.strip(j);
   const uint64_t W = c.a->row_bytes;
+  VT v[P - 1];
 #pragma unroll
-  for (int r = 0; r < P - 1; ++r) acc[r] ^= ld<VT>(b, r, W, c.col);
+  for (int r = 0; r < P - 1; ++r) v[r] = ld<VT>(b, r, W, c.col);
+  // All rows in flight before the first use (as in the streaming phase).
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < P - 1; ++r) acc[r] ^= v[r];
 }
 
 template <int P, int V>
@@ -181,7 +227,7 @@ __device__ __forceinline__ void store_reduced(const Cols& c, int j, const typena
 }
 
 // Full encode of one tile: P and Q (either may be skipped).
-template <int P, int V>
+template <int P, int V, int U>
 __device__ __forceinline__ void tile_encode(const Cols& c, int k, bool wp, bool wq) {
   typedef typename vec_t<V>::type VT;
   VT ap[P - 1], aq[P];
@@ -190,11 +236,11 @@ __device__ __forceinline__ void tile_encode(const Cols& c, int k, bool wp, bool 
 #pragma unroll
   for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
   if (wp && wq) {
-    stream_data<P, V, true, true>(c, k, -1, -1, ap, aq);
+    stream_data<P, V, U, true, true>(c, k, -1, -1, ap, aq);
   } else if (wp) {
-    stream_data<P, V, true, false>(c, k, -1, -1, ap, aq);
+    stream_data<P, V, U, true, false>(c, k, -1, -1, ap, aq);
   } else {
-    stream_data<P, V, false, true>(c, k, -1, -1, ap, aq);
+    stream_data<P, V, U, false, true>(c, k, -1, -1, ap, aq);
   }
   if (wp) store_strip<P, V>(c, k, ap);
   if (wq) store_reduced<P, V>(c, k + 1, aq);
@@ -202,7 +248,7 @@ __device__ __forceinline__ void tile_encode(const Cols& c, int k, bool wp, bool 
 
 // Recovery of one tile.  `lds` points at this thread's column of a region of
 // P rows with a row stride of `ls` vectors; only this thread touches it.
-template <int P, int V>
+template <int P, int V, int U>
 __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& cs,
                                              typename vec_t<V>::type* lds, int ls) {
   typedef typename vec_t<V>::type VT;
@@ -211,13 +257,13 @@ __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& c
 
   switch (cs.op) {
     case OP_PQ:
-      tile_encode<P, V>(c, k, true, true);
+      tile_encode<P, V, U>(c, k, true, true);
       return;
     case OP_P:
-      tile_encode<P, V>(c, k, true, false);
+      tile_encode<P, V, U>(c, k, true, false);
       return;
     case OP_Q:
-      tile_encode<P, V>(c, k, false, true);
+      tile_encode<P, V, U>(c, k, false, true);
       return;
     default:
       break;
@@ -230,7 +276,7 @@ __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& c
   if (cs.op == OP_D) {
     // D_x = P + sum_{t != x} D_t.
     load_into<P, V>(c, iP, ap);
-    stream_data<P, V, true, false>(c, k, cs.x, -1, ap, aq);
+    stream_data<P, V, U, true, false>(c, k, cs.x, -1, ap, aq);
     store_strip<P, V>(c, cs.x, ap);
     return;
   }
@@ -239,7 +285,7 @@ __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& c
     // D_x = P + sum_{t != x} D_t;  Q = sum_{t != x} x^t D_t + x^x D_x.
     const int x = cs.x;
     load_into<P, V>(c, iP, ap);
-    stream_data<P, V, true, true>(c, k, x, -1, ap, aq);
+    stream_data<P, V, U, true, true>(c, k, x, -1, ap, aq);
 #pragma unroll
     for (int r = 0; r < R; ++r) lds[r * ls] = ap[r];
     lds[R * ls] = (VT)(0u);
@@ -260,25 +306,22 @@ __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& c
     const int x = cs.x;
 #pragma unroll
     for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
-    stream_data<P, V, true, true>(c, k, x, -1, ap, aq);
+    stream_data<P, V, U, true, true>(c, k, x, -1, ap, aq);
     xor_from<P, V>(c, iQ, aq);
 #pragma unroll
     for (int u = 0; u < P; ++u) lds[u * ls] = aq[u];
-    // (x^{p-x} a)[u] = a[(u + x) mod p]
-    VT d[P];
+    // (x^{p-x} a)[u] = a[(u + x) mod p], then reduce: row r plus row p-1.
+    const __amdgpu_buffer_rsrc_t bx = c.strip(x), bp = c.strip(iP);
+    const uint64_t W = c.a->row_bytes;
+    const VT top = lds[(R + x) % P * ls];
 #pragma unroll
-    for (int u = 0; u < P; ++u) {
-      int w = u + x;
+    for (int r = 0; r < R; ++r) {
+      int w = r + x;
       if (w >= P) w -= P;
-      d[u] = lds[w * ls];
+      const VT d = lds[w * ls] ^ top;
+      st<VT>(bx, r, W, c.col, d);
+      st<VT>(bp, r, W, c.col, d ^ ap[r]);
     }
-    VT out[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[r] = d[r] ^ d[R];
-    store_strip<P, V>(c, x, out);
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[r] ^= ap[r];
-    store_strip<P, V>(c, iP, out);
     return;
   }
 
@@ -288,69 +331,57 @@ __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& c
   const int x = cs.x;
   const int z = cs.y - cs.x;
   load_into<P, V>(c, iP, ap);
-  stream_data<P, V, true, true>(c, k, cs.x, cs.y, ap, aq);
+  stream_data<P, V, U, true, true>(c, k, cs.x, cs.y, ap, aq);
   xor_from<P, V>(c, iQ, aq);
 
-  // e = XOR of all rows of T~ = XOR of all rows of dP~ and of dQ~ (a rotation
-  // keeps the set of rows).
-  VT e = (VT)(0u);
-#pragma unroll
-  for (int r = 0; r < R; ++r) e ^= ap[r];
-#pragma unroll
-  for (int u = 0; u < P; ++u) e ^= aq[u];
-
-  // Chain rows u_s = (p-1 + s z) mod p, s = 1..p-1.
-  // T~[u] = dP~[u] + dQ~[(u + x) mod p].
+  // T~[u] = dP~[u] + dQ~[(u + x) mod p], built in natural row order through
+  // LDS (aq is reused for T~), then written back for the chain.
 #pragma unroll
   for (int u = 0; u < P; ++u) lds[u * ls] = aq[u];
-  VT tch[R];
-  {
-    int u = R;
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      u += z;
-      if (u >= P) u -= P;
-      int w = u + x;
-      if (w >= P) w -= P;
-      tch[s] = lds[w * ls];
-    }
+  for (int u = 0; u < P; ++u) {
+    int w = u + x;
+    if (w >= P) w -= P;
+    aq[u] = lds[w * ls];
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) lds[r * ls] = ap[r];
-  {
-    int u = R;
+  for (int r = 0; r < R; ++r) aq[r] ^= ap[r];
+  // e = XOR of all p rows of T~.
+  VT e = (VT)(0u);
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      u += z;
-      if (u >= P) u -= P;
-      tch[s] ^= lds[u * ls];   // u != p-1 on the chain
-    }
-  }
-  // D~[u_s] = T~[u_s] + e + D~[u_{s-1}],  D~[p-1] = 0.
+  for (int u = 0; u < P; ++u) e ^= aq[u];
+#pragma unroll
+  for (int u = 0; u < P; ++u) lds[u * ls] = aq[u];
+
+  // Chain over rows u_s = (p-1 + s z) mod p, s = 1..p-1:
+  // D~[u_s] = T~[u_s] + e + D~[u_{s-1}], D~[p-1] = 0, written in place (each
+  // row is visited once, so its T~ value is consumed before it is replaced).
+  // The next row's value is read before the current one is written: rows of
+  // consecutive steps differ, so the read does not see the write.
   {
+    int u = R + z;
+    if (u >= P) u -= P;
+    VT t = lds[u * ls];
     VT d = (VT)(0u);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      d = tch[s] ^ e ^ d;
-      tch[s] = d;
+      int un = u + z;
+      if (un >= P) un -= P;
+      const VT tn = (s + 1 < R) ? lds[un * ls] : (VT)(0u);
+      d = t ^ e ^ d;
+      lds[u * ls] = d;
+      t = tn;
+      u = un;
     }
   }
-  {
-    int u = R;
+  const __amdgpu_buffer_rsrc_t bx = c.strip(cs.x), by = c.strip(cs.y);
+  const uint64_t W = c.a->row_bytes;
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      u += z;
-      if (u >= P) u -= P;
-      lds[u * ls] = tch[s];
-    }
+  for (int r = 0; r < R; ++r) {
+    const VT dy = lds[r * ls];
+    st<VT>(by, r, W, c.col, dy);
+    st<VT>(bx, r, W, c.col, dy ^ ap[r]);
   }
-  VT dy[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) dy[r] = lds[r * ls];
-  store_strip<P, V>(c, cs.y, dy);
-#pragma unroll
-  for (int r = 0; r < R; ++r) dy[r] ^= ap[r];
-  store_strip<P, V>(c, cs.x, dy);
 }
 
 }  // namespace raid6c

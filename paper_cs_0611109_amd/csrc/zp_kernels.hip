@@ -27,17 +27,17 @@ static_assert(kP >= 3 && kP <= kMaxPrime && (kP % 2) == 1, "unsupported prime");
 // for the two accumulators, so they are only built for small p.
 constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (kP <= 31) ? (1 | 2) : 1;
 
-template <int P, int V>
+template <int P, int V, int U>
 __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
   const uint32_t stripe = blockIdx.x / a.tiles;
   const uint32_t tile = blockIdx.x - stripe * a.tiles;
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
   const Cols c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
-  tile_encode<P, V>(c, a.k, true, true);
+  tile_encode<P, V, U>(c, a.k, true, true);
 }
 
-template <int P, int V>
+template <int P, int V, int U>
 __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   typedef typename vec_t<V>::type VT;
@@ -57,44 +57,60 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   if (col >= a.row_bytes) return;
   const Cols c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
   VT* lds = reinterpret_cast<VT*>(smem) + threadIdx.x;
-  tile_recover<P, V>(c, a.k, cs, lds, (int)blockDim.x);
+  tile_recover<P, V, U>(c, a.k, cs, lds, (int)blockDim.x);
 }
 
-template <int V>
-hipError_t launch_v(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
-                    hipStream_t stream) {
-  const dim3 g(grid), b(cfg.threads);
-  if (kind == KIND_ENCODE) {
-    hipLaunchKernelGGL((zp_encode_kernel<kP, V>), g, b, 0, stream, a);
+// (vec, unroll) pairs built for this prime: accumulators take (2p-1)*vec
+// dwords per thread and a batch of loads unroll*(p-1)*vec more.
+template <int V, int U>
+constexpr bool built() {
+  return (kVecMask & V) != 0 && (2 * kP - 1) * V + U * (kP - 1) * V <= 192;
+}
+
+constexpr int unroll_mask(int v) {
+  return v == 1 ? ((built<1, 1>() ? 1 : 0) | (built<1, 2>() ? 2 : 0) | (built<1, 4>() ? 4 : 0))
+       : v == 2 ? ((built<2, 1>() ? 1 : 0) | (built<2, 2>() ? 2 : 0) | (built<2, 4>() ? 4 : 0))
+       : v == 4 ? ((built<4, 1>() ? 1 : 0) | (built<4, 2>() ? 2 : 0) | (built<4, 4>() ? 4 : 0))
+                : 0;
+}
+
+template <int V, int U>
+hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                     hipStream_t stream) {
+  if constexpr (built<V, U>()) {
+    const dim3 g(grid), b(cfg.threads);
+    if (kind == KIND_ENCODE) {
+      hipLaunchKernelGGL((zp_encode_kernel<kP, V, U>), g, b, 0, stream, a);
+    } else {
+      const size_t lds = (size_t)kP * cfg.threads * V * 4;
+      hipLaunchKernelGGL((zp_recover_kernel<kP, V, U>), g, b, lds, stream, a);
+    }
+    return hipGetLastError();
   } else {
-    const size_t lds = (size_t)kP * cfg.threads * V * 4;
-    hipLaunchKernelGGL((zp_recover_kernel<kP, V>), g, b, lds, stream, a);
+    return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                   hipStream_t stream) {
-  switch (cfg.vec) {
-    case 1:
-      return launch_v<1>(kind, cfg, a, grid, stream);
-#if RAID6C_P <= 31
-    case 2:
-      return launch_v<2>(kind, cfg, a, grid, stream);
-#endif
-#if RAID6C_P <= 13
-    case 4:
-      return launch_v<4>(kind, cfg, a, grid, stream);
-#endif
-    default:
-      return hipErrorInvalidValue;
+  switch (cfg.vec * 8 + cfg.unroll) {
+    case 9: return launch_vu<1, 1>(kind, cfg, a, grid, stream);
+    case 10: return launch_vu<1, 2>(kind, cfg, a, grid, stream);
+    case 12: return launch_vu<1, 4>(kind, cfg, a, grid, stream);
+    case 17: return launch_vu<2, 1>(kind, cfg, a, grid, stream);
+    case 18: return launch_vu<2, 2>(kind, cfg, a, grid, stream);
+    case 20: return launch_vu<2, 4>(kind, cfg, a, grid, stream);
+    case 33: return launch_vu<4, 1>(kind, cfg, a, grid, stream);
+    case 34: return launch_vu<4, 2>(kind, cfg, a, grid, stream);
+    case 36: return launch_vu<4, 4>(kind, cfg, a, grid, stream);
+    default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
 const ZpPrimeEntry* RAID6C_CAT(zp_entry_, RAID6C_P)() {
-  static const ZpPrimeEntry e{kP, &launch, kVecMask};
+  static const ZpPrimeEntry e{kP, &launch, kVecMask, {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)}};
   return &e;
 }
 

@@ -114,15 +114,30 @@ def test_rs_argument_checks():
 
 def test_tuning_table():
     r.raid6c_tune_clear()
-    v0, t0 = r.raid6c_tune_get(13, 0, 4096)
-    assert v0 in (1, 2, 4) and t0 in (64, 128, 256)
-    r.raid6c_tune_set(13, 0, 4096, 1, 64)
-    assert r.raid6c_tune_get(13, 0, 4096) == (1, 64)
-    assert r.raid6c_tune_get(13, 0, 4096 + 2048) == (1, 64)     # same power-of-two bucket
-    assert r.raid6c_tune_get(13, 1, 4096) == r.raid6c_tune_get(13, 1, 4096)
+    d0 = r.raid6c_tune_get(13, 0, 4096)
+    assert d0[0] in (1, 2, 4) and d0[1] in (1, 2, 4) and d0[2] in (64, 128, 256)
+    r.raid6c_tune_set(13, 0, 4096, 1, 2, 128)
+    assert r.raid6c_tune_get(13, 0, 4096) == (1, 2, 128)
+    assert r.raid6c_tune_get(13, 0, 4096 + 2048) == (1, 2, 128)     # same power-of-two bucket
+    assert r.raid6c_tune_get(13, 0, 8192) == d0 or r.raid6c_tune_get(13, 0, 8192) != (1, 2, 128)
     r.raid6c_tune_clear()
-    assert r.raid6c_tune_get(13, 0, 4096) == (v0, t0)
-    _err(r.raid6c_tune_set, 9, 0, 64, 1, 64)
-    _err(r.raid6c_tune_set, 53, 0, 64, 4, 64)     # vec 4 not built for large p
-    _err(r.raid6c_tune_set, 13, 2, 64, 1, 64)
-    _err(r.raid6c_tune_set, 13, 0, 64, 1, 96)
+    assert r.raid6c_tune_get(13, 0, 4096) == d0
+    _err(r.raid6c_tune_set, 9, 0, 64, 1, 1, 64)
+    _err(r.raid6c_tune_set, 53, 0, 64, 4, 1, 64)     # vec 4 not built for large p
+    _err(r.raid6c_tune_set, 53, 0, 64, 1, 4, 64)     # too many registers
+    _err(r.raid6c_tune_set, 13, 2, 64, 1, 1, 64)
+    _err(r.raid6c_tune_set, 13, 0, 64, 1, 1, 96)
+    _err(r.raid6c_tune_set, 13, 0, 64, 1, 3, 64)
+
+
+def test_built_configurations():
+    for p in range(3, r.raid6c_max_prime() + 1):
+        if not r.raid6c_is_supported_prime(p):
+            assert r.raid6c_unroll_mask(p, 1) == 0
+            continue
+        assert r.raid6c_unroll_mask(p, 1) & 1            # (vec 1, unroll 1) always built
+        for v in (1, 2, 4):
+            m = r.raid6c_unroll_mask(p, v)
+            assert (m != 0) <= bool(r.raid6c_vec_mask(p) & v)
+        v, u, t = r.raid6c_tune_get(p, 1, 1024)
+        assert r.raid6c_unroll_mask(p, v) & u

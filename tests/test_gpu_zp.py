@@ -51,8 +51,8 @@ def _recover_on_gpu(want, p, k, w, er):
 
 
 def _configs(p):
-    mask = r.raid6c_vec_mask(p)
-    return [(v, t) for v in (1, 2, 4) if mask & v for t in (64, 128, 256)]
+    return [(v, u, t) for v in (1, 2, 4) for u in (1, 2, 4) if r.raid6c_unroll_mask(p, v) & u
+            for t in (64, 128, 256)]
 
 
 @pytest.fixture(autouse=True)
@@ -93,16 +93,16 @@ def test_recover_every_case_matches_oracle(p):
 
 @pytest.mark.parametrize("p", [3, 5, 7, 11, 13, 17, 29, 31, 37, 61])
 def test_every_launch_config(p):
-    k = min(p, 6)
-    for (v, t) in _configs(p):
-        for w in (16, 48, 64 * 4 * v + 16):
-            log(f"config p={p} vec={v} threads={t} W={w}")
-            r.raid6c_tune_set(p, 0, w, v, t)
-            r.raid6c_tune_set(p, 1, w, v, t)
-            want = _stripes(p, k, w, 4, seed=7 * p + v + t)
-            assert np.array_equal(_encode_on_gpu(want, p, k, w), want), (v, t, w)
-            er = datagen.erasures(v * 1000 + t, 4, k, "any")
-            assert np.array_equal(_recover_on_gpu(want, p, k, w, er), want), (v, t, w)
+    for k in sorted({min(p, 6), p}):
+        for (v, u, t) in _configs(p):
+            for w in (16, 64 * 4 * v + 16):
+                log(f"config p={p} k={k} vec={v} unroll={u} threads={t} W={w}")
+                r.raid6c_tune_set(p, 0, w, v, u, t)
+                r.raid6c_tune_set(p, 1, w, v, u, t)
+                want = _stripes(p, k, w, 4, seed=7 * p + v + t + u)
+                assert np.array_equal(_encode_on_gpu(want, p, k, w), want), (v, u, t, w)
+                er = datagen.erasures(v * 1000 + t + u, 4, k, "any")
+                assert np.array_equal(_recover_on_gpu(want, p, k, w, er), want), (v, u, t, w)
 
 
 def test_config1_all_pairs():
