@@ -145,6 +145,91 @@ int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base,
                        void* stream);
 
 /* ------------------------------------------------------------------------
+ * Plans: many stripes of mixed p, k and row size in one persistent launch
+ *
+ * A plan is built once from a job list and replayed any number of times.
+ * Each replay is one HIP graph launch holding a single persistent kernel
+ * (plus a one-thread kernel that resets its work counter): every stripe's
+ * columns are cut into 256-byte work items that single-wave work-groups take
+ * from a device counter, largest stripes first.  The per-stripe math is that
+ * of raid6c_encode / raid6c_recover_1 / raid6c_recover_2, bit for bit.
+ * ------------------------------------------------------------------------ */
+
+#define RAID6C_JOB_ENCODE   0  /* write P and Q from the data strips */
+#define RAID6C_JOB_RECOVER  1  /* rebuild strips e0 (and e1, unless -1) */
+
+/* One stripe of a plan: strip j (0..k-1 data, k = P, k+1 = Q) starts at
+ * base + j*strip_stride (device memory, 16-byte aligned, strip_stride a
+ * multiple of 16 and >= (p-1)*row_bytes).  Strips of different jobs must not
+ * share any byte.  e0/e1 are ignored for encode jobs. */
+typedef struct raid6c_job {
+  int32_t op;
+  int32_t p;
+  int32_t k;
+  int32_t e0;
+  int32_t e1;
+  uint32_t row_bytes;
+  uint64_t strip_stride;
+  void* base;
+} raid6c_job;
+
+#define RAID6C_ORDER_LARGEST_FIRST 0  /* items of the costliest stripes first */
+#define RAID6C_ORDER_BY_PRIME      1  /* grouped by p (largest p first) */
+#define RAID6C_ORDER_SUBMITTED     2  /* job order as given */
+
+/* Schedule of a plan: persistent work-groups per compute unit, work items
+ * taken per counter increment, and item order.  Changes speed only. */
+typedef struct raid6c_schedule {
+  int32_t waves_per_cu;  /* 1..32 */
+  int32_t chunk;         /* 1..1024 */
+  int32_t order;         /* RAID6C_ORDER_* */
+} raid6c_schedule;
+
+typedef struct raid6c_plan_info {
+  uint64_t njobs;
+  uint64_t nitems;
+  uint64_t bytes_moved;  /* algorithmic HBM bytes per run */
+  uint64_t user_bytes;   /* sum of k*(p-1)*row_bytes */
+  int32_t max_p;
+  int32_t grid;          /* persistent work-groups per launch */
+} raid6c_plan_info;
+
+typedef struct raid6c_plan raid6c_plan;
+
+/* Build a plan for njobs jobs on the current device.  The plan owns device
+ * memory for its job and item tables (freed by raid6c_plan_destroy) and keeps
+ * the job addresses, which must stay valid while the plan is used.  This call
+ * synchronises with the device (uploads).  Errors: RAID6C_E_ARG for an
+ * invalid job (its index is in raid6c_last_error()) or overlapping strips,
+ * RAID6C_E_UNSUPPORTED for p above raid6c_max_prime(), RAID6C_E_NOMEM,
+ * RAID6C_E_HIP.  njobs = 0 gives an empty plan whose runs do nothing. */
+int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out);
+
+/* Enqueue one run of the plan on `stream` (a graph launch).  Runs are
+ * idempotent: every job rewrites the same bytes.  Runs of one plan on
+ * different streams must not overlap in time (they share the work counter).
+ * Errors: RAID6C_E_ARG (NULL plan), RAID6C_E_HIP. */
+int raid6c_plan_run(raid6c_plan* plan, void* stream);
+
+/* Current schedule / replace it (rebuilds the graph; synchronises).
+ * Errors: RAID6C_E_ARG for NULL arguments or an invalid schedule. */
+int raid6c_plan_get_schedule(const raid6c_plan* plan, raid6c_schedule* out);
+int raid6c_plan_set_schedule(raid6c_plan* plan, const raid6c_schedule* schedule);
+
+/* Sizes of the plan.  Errors: RAID6C_E_ARG for NULL arguments. */
+int raid6c_plan_stats(const raid6c_plan* plan, raid6c_plan_info* out);
+
+/* Autotuner: time every candidate schedule (waves per CU x chunk x order)
+ * over `reps` runs each on `stream`, keep the fastest, and return its mean
+ * time per run in *best_ms (may be NULL).  Runs the plan (reps+1) times per
+ * candidate, which rewrites the same output bytes.  Synchronises.
+ * Errors: RAID6C_E_ARG (NULL plan, reps outside 1..1000), RAID6C_E_HIP. */
+int raid6c_plan_autotune(raid6c_plan* plan, void* stream, int reps, float* best_ms);
+
+/* Free the plan and its device memory (NULL is allowed). */
+int raid6c_plan_destroy(raid6c_plan* plan);
+
+/* ------------------------------------------------------------------------
  * Launch configuration (used by the autotuner and by tests)
  *
  * A Z_p kernel launch is configured by `vec`, the dwords each thread moves

@@ -7,6 +7,21 @@ same names, plus a helper that lays stripes out in one device tensor.
 
 from ._lib import (  # noqa: F401
     LIB_PATH,
+    RAID6C_JOB_ENCODE,
+    RAID6C_JOB_RECOVER,
+    RAID6C_ORDER_BY_PRIME,
+    RAID6C_ORDER_LARGEST_FIRST,
+    RAID6C_ORDER_SUBMITTED,
+    raid6c_job,
+    raid6c_plan_autotune,
+    raid6c_plan_create,
+    raid6c_plan_destroy,
+    raid6c_plan_get_schedule,
+    raid6c_plan_info,
+    raid6c_plan_run,
+    raid6c_plan_set_schedule,
+    raid6c_plan_stats,
+    raid6c_schedule,
     RAID6C_E_ARG,
     RAID6C_E_HIP,
     RAID6C_E_NOMEM,

@@ -42,7 +42,37 @@ SIGNATURES = {
     "raid6c_tune_get": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
                                  ctypes.POINTER(_c_int)]),
     "raid6c_tune_clear": (None, []),
+    "raid6c_plan_create": (_c_int, [_vp, _c_size, _vp]),
+    "raid6c_plan_run": (_c_int, [_vp, _vp]),
+    "raid6c_plan_get_schedule": (_c_int, [_vp, _vp]),
+    "raid6c_plan_set_schedule": (_c_int, [_vp, _vp]),
+    "raid6c_plan_stats": (_c_int, [_vp, _vp]),
+    "raid6c_plan_autotune": (_c_int, [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_float)]),
+    "raid6c_plan_destroy": (_c_int, [_vp]),
 }
+
+
+
+class raid6c_job(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("p", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("e0", ctypes.c_int32), ("e1", ctypes.c_int32), ("row_bytes", ctypes.c_uint32),
+                ("strip_stride", ctypes.c_uint64), ("base", ctypes.c_void_p)]
+
+
+class raid6c_schedule(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
+class raid6c_plan_info(ctypes.Structure):
+    _fields_ = [("njobs", ctypes.c_uint64), ("nitems", ctypes.c_uint64), ("bytes_moved", ctypes.c_uint64),
+                ("user_bytes", ctypes.c_uint64), ("max_p", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+
+RAID6C_JOB_ENCODE = 0
+RAID6C_JOB_RECOVER = 1
+RAID6C_ORDER_LARGEST_FIRST = 0
+RAID6C_ORDER_BY_PRIME = 1
+RAID6C_ORDER_SUBMITTED = 2
 
 _lib = None
 
@@ -178,3 +208,43 @@ def raid6c_tune_get(p, op, row_bytes):
 
 def raid6c_tune_clear():
     load().raid6c_tune_clear()
+
+
+def raid6c_plan_create(jobs) -> int:
+    """``jobs``: sequence of raid6c_job (or a ctypes array of them).  Returns
+    the plan handle (an int); free it with raid6c_plan_destroy."""
+    arr = jobs if isinstance(jobs, ctypes.Array) else (raid6c_job * len(jobs))(*jobs)
+    out = _vp()
+    _check(load().raid6c_plan_create(ctypes.cast(arr, _vp) if len(arr) else None, len(arr), ctypes.byref(out)))
+    return out.value
+
+
+def raid6c_plan_run(plan, stream=None):
+    return _check(load().raid6c_plan_run(plan, _stream(stream)))
+
+
+def raid6c_plan_get_schedule(plan) -> raid6c_schedule:
+    s = raid6c_schedule()
+    _check(load().raid6c_plan_get_schedule(plan, ctypes.byref(s)))
+    return s
+
+
+def raid6c_plan_set_schedule(plan, waves_per_cu, chunk, order):
+    s = raid6c_schedule(waves_per_cu, chunk, order)
+    return _check(load().raid6c_plan_set_schedule(plan, ctypes.byref(s)))
+
+
+def raid6c_plan_stats(plan) -> raid6c_plan_info:
+    i = raid6c_plan_info()
+    _check(load().raid6c_plan_stats(plan, ctypes.byref(i)))
+    return i
+
+
+def raid6c_plan_autotune(plan, stream=None, reps=3) -> float:
+    ms = ctypes.c_float()
+    _check(load().raid6c_plan_autotune(plan, _stream(stream), reps, ctypes.byref(ms)))
+    return ms.value
+
+
+def raid6c_plan_destroy(plan):
+    return _check(load().raid6c_plan_destroy(plan))

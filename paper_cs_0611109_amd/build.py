@@ -28,7 +28,7 @@ CFLAGS = [
 ]
 
 # Plain (non-templated-per-prime) sources.
-SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip"]
+SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip", "batch.hip"]
 
 
 def _units(build_dir):

@@ -1,0 +1,431 @@
+// batch.hip -- plans: stripes of mixed p, k and row size, encoded and
+// recovered in one persistent kernel launch replayed from a HIP graph.
+//
+// Work is cut into items of one wavefront each: 64 lanes x 4 bytes = a
+// 256-byte column tile of one stripe.  A persistent grid of single-wave
+// work-groups pops items from a device counter (a chunk at a time) and runs
+// the same per-tile code as the plain kernels (tile_recover: encode is the
+// "P and Q erased" case), dispatched on the stripe's prime.  Items are
+// ordered largest-first so the tail of the launch is made of small items.
+//
+// The graph holds two nodes: a one-thread kernel that zeroes the counter
+// (a kernel, not a memset node) and the persistent kernel.
+#include <hip/hip_runtime.h>
+
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "../../include/raid6c.h"
+#include "raid6c_internal.h"
+#include "zp_core.hpp"
+
+namespace raid6c {
+
+int fail(int code, const char* fmt, ...);
+
+namespace {
+
+struct BatchJob {
+  uint8_t* base;          // strip 0
+  uint64_t strip_stride;  // bytes between strips
+  uint32_t row_bytes;
+  int16_t p, k;
+  int16_t op, x, y, pad;  // Case
+};
+
+struct BatchItem {
+  uint32_t job;
+  uint32_t col;  // byte offset of the 256-byte tile within a row
+};
+
+struct BatchArgs {
+  const BatchJob* jobs;
+  const BatchItem* items;
+  uint32_t nitems;
+  uint32_t chunk;  // items taken per counter increment
+  uint32_t* counter;
+};
+
+constexpr int kLanes = 64;
+constexpr int kTileBytes = kLanes * 4;  // one dword per lane and row
+
+// Strips whose loads are batched per prime: as many as fit beside the
+// (2p-1) accumulator dwords in the register budget set by the largest prime
+// (about 160 dwords), never more than p.
+constexpr int batch_unroll(int p) {
+  const int cap = (160 - (2 * p - 1)) / (p - 1);
+  const int u = cap < 1 ? 1 : cap;
+  return u > p ? p : u;
+}
+
+template <int P>
+__device__ __forceinline__ void run_item(const BatchJob& j, uint32_t col, uint32_t* lds) {
+  const ColsStrided c{j.base, j.strip_stride, j.row_bytes, col, (uint32_t)((P - 1) * j.row_bytes)};
+  const Case cs{j.op, j.x, j.y};
+  tile_recover<P, 1, batch_unroll(P)>(c, j.k, cs, lds, kLanes);
+}
+
+__global__ void reset_counter(uint32_t* counter) { *counter = 0u; }
+
+__global__ void __launch_bounds__(64) batch_kernel(const BatchArgs a) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  const uint32_t lane = threadIdx.x;
+  uint32_t* lds = smem + lane;
+  for (;;) {
+    uint32_t got = 0;
+    if (lane == 0) got = atomicAdd(a.counter, a.chunk);
+    const uint32_t first = __builtin_amdgcn_readfirstlane(got);
+    if (first >= a.nitems) break;
+    const uint32_t last = min(first + a.chunk, a.nitems);
+    for (uint32_t it = first; it < last; ++it) {
+      const BatchItem item = a.items[it];
+      const BatchJob j = a.jobs[item.job];
+      const uint32_t col = item.col + lane * 4u;
+      if (col >= j.row_bytes) continue;
+      switch (j.p) {
+#define RAID6C_BATCH_CASE(q) \
+  case q:                    \
+    run_item<q>(j, col, lds); \
+    break;
+        RAID6C_BATCH_CASE(3)
+        RAID6C_BATCH_CASE(5)
+        RAID6C_BATCH_CASE(7)
+        RAID6C_BATCH_CASE(11)
+        RAID6C_BATCH_CASE(13)
+        RAID6C_BATCH_CASE(17)
+        RAID6C_BATCH_CASE(19)
+        RAID6C_BATCH_CASE(23)
+        RAID6C_BATCH_CASE(29)
+        RAID6C_BATCH_CASE(31)
+        RAID6C_BATCH_CASE(37)
+        RAID6C_BATCH_CASE(41)
+        RAID6C_BATCH_CASE(43)
+        RAID6C_BATCH_CASE(47)
+        RAID6C_BATCH_CASE(53)
+        RAID6C_BATCH_CASE(59)
+        RAID6C_BATCH_CASE(61)
+#undef RAID6C_BATCH_CASE
+        default:
+          break;
+      }
+    }
+  }
+}
+
+bool is_odd_prime(int p) {
+  if (p < 3 || (p % 2) == 0) return false;
+  for (int d = 3; d * d <= p; d += 2)
+    if (p % d == 0) return false;
+  return true;
+}
+
+}  // namespace
+
+}  // namespace raid6c
+
+using namespace raid6c;
+
+struct raid6c_plan {
+  int device = 0;
+  std::vector<BatchJob> jobs;
+  std::vector<BatchItem> items;   // current order
+  std::vector<uint64_t> job_cost; // bytes moved per tile, per job
+  void* dmem = nullptr;           // jobs | items | counter
+  BatchArgs args{};
+  int max_p = 3;
+  int cus = 256;
+  raid6c_schedule sched{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t bytes = 0;             // algorithmic bytes per run
+  uint64_t user_bytes = 0;
+};
+
+namespace {
+
+void order_items(raid6c_plan* pl, int order) {
+  const size_t nj = pl->jobs.size();
+  std::vector<uint32_t> idx(nj);
+  for (size_t i = 0; i < nj; ++i) idx[i] = (uint32_t)i;
+  if (order == RAID6C_ORDER_LARGEST_FIRST) {
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](uint32_t a, uint32_t b) { return pl->job_cost[a] > pl->job_cost[b]; });
+  } else if (order == RAID6C_ORDER_BY_PRIME) {
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+      if (pl->jobs[a].p != pl->jobs[b].p) return pl->jobs[a].p > pl->jobs[b].p;
+      return pl->job_cost[a] > pl->job_cost[b];
+    });
+  }
+  pl->items.clear();
+  for (uint32_t j : idx) {
+    const uint32_t w = pl->jobs[j].row_bytes;
+    for (uint32_t c = 0; c < w; c += kTileBytes) pl->items.push_back(BatchItem{j, c});
+  }
+}
+
+void free_graph(raid6c_plan* pl) {
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  pl->exec = nullptr;
+  pl->graph = nullptr;
+}
+
+// Upload the item order and (re)build the two-node graph for the current
+// schedule.
+int build_graph(raid6c_plan* pl) {
+  free_graph(pl);
+  hipError_t e = hipMemcpy((void*)pl->args.items, pl->items.data(), pl->items.size() * sizeof(BatchItem),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(RAID6C_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
+  pl->args.chunk = (uint32_t)pl->sched.chunk;
+  if ((e = hipGraphCreate(&pl->graph, 0)) != hipSuccess)
+    return fail(RAID6C_E_HIP, "hipGraphCreate: %s", hipGetErrorString(e));
+
+  hipGraphNode_t reset_node, batch_node;
+  void* reset_params[] = {(void*)&pl->args.counter};
+  hipKernelNodeParams rp{};
+  rp.func = (void*)reset_counter;
+  rp.gridDim = dim3(1);
+  rp.blockDim = dim3(1);
+  rp.sharedMemBytes = 0;
+  rp.kernelParams = reset_params;
+  if ((e = hipGraphAddKernelNode(&reset_node, pl->graph, nullptr, 0, &rp)) != hipSuccess)
+    return fail(RAID6C_E_HIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+
+  void* batch_params[] = {(void*)&pl->args};
+  hipKernelNodeParams bp{};
+  bp.func = (void*)batch_kernel;
+  bp.gridDim = dim3((unsigned)(pl->cus * pl->sched.waves_per_cu));
+  bp.blockDim = dim3(kLanes);
+  bp.sharedMemBytes = (unsigned)(pl->max_p * kLanes * 4);
+  bp.kernelParams = batch_params;
+  if ((e = hipGraphAddKernelNode(&batch_node, pl->graph, &reset_node, 1, &bp)) != hipSuccess)
+    return fail(RAID6C_E_HIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+  if ((e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return fail(RAID6C_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  return RAID6C_OK;
+}
+
+bool valid_schedule(const raid6c_schedule& s) {
+  return s.waves_per_cu >= 1 && s.waves_per_cu <= 32 && s.chunk >= 1 && s.chunk <= 1024 &&
+         (s.order == RAID6C_ORDER_LARGEST_FIRST || s.order == RAID6C_ORDER_BY_PRIME ||
+          s.order == RAID6C_ORDER_SUBMITTED);
+}
+
+}  // namespace
+
+extern "C" {
+
+int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) {
+  if (out == nullptr) return fail(RAID6C_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (jobs == nullptr && njobs != 0) return fail(RAID6C_E_ARG, "jobs is NULL");
+  if (njobs > 0xFFFFFFFFull) return fail(RAID6C_E_ARG, "too many jobs");
+  raid6c_plan* pl = new (std::nothrow) raid6c_plan();
+  if (pl == nullptr) return fail(RAID6C_E_NOMEM, "out of host memory");
+
+  // Check every job and every strip interval (no two jobs may share bytes).
+  struct Span {
+    uintptr_t lo, hi;
+    uint32_t job;
+  };
+  std::vector<Span> spans;
+  pl->jobs.reserve(njobs);
+  for (size_t i = 0; i < njobs; ++i) {
+    const raid6c_job& J = jobs[i];
+    const int p = J.p, k = J.k;
+    int rc = RAID6C_OK;
+    if (!is_odd_prime(p)) rc = fail(RAID6C_E_ARG, "job %zu: p = %d is not an odd prime", i, p);
+    else if (p > kMaxPrime) rc = fail(RAID6C_E_UNSUPPORTED, "job %zu: p = %d is not built", i, p);
+    else if (k < 1 || k > p) rc = fail(RAID6C_E_ARG, "job %zu: k = %d not in [1, %d]", i, k, p);
+    else if (J.row_bytes == 0 || (J.row_bytes % 16) != 0)
+      rc = fail(RAID6C_E_ARG, "job %zu: row_bytes must be a positive multiple of 16", i);
+    else if ((uint64_t)(p - 1) * J.row_bytes >= (1ull << 31))
+      rc = fail(RAID6C_E_ARG, "job %zu: strip of 2 GiB or more", i);
+    else if (J.base == nullptr || ((uintptr_t)J.base & 15u) != 0)
+      rc = fail(RAID6C_E_ARG, "job %zu: base is NULL or not 16-byte aligned", i);
+    else if ((J.strip_stride % 16) != 0 || J.strip_stride < (uint64_t)(p - 1) * J.row_bytes)
+      rc = fail(RAID6C_E_ARG, "job %zu: bad strip_stride", i);
+    else if (J.op != RAID6C_JOB_ENCODE && J.op != RAID6C_JOB_RECOVER)
+      rc = fail(RAID6C_E_ARG, "job %zu: op must be encode or recover", i);
+    Case cs{OP_PQ, -1, -1};
+    if (rc == RAID6C_OK && J.op == RAID6C_JOB_RECOVER) {
+      cs = classify(k, J.e0, J.e1);
+      if (cs.op == OP_BAD) rc = fail(RAID6C_E_ARG, "job %zu: invalid erasures (%d, %d)", i, J.e0, J.e1);
+    }
+    if (rc != RAID6C_OK) {
+      delete pl;
+      return rc;
+    }
+    BatchJob b{};
+    b.base = (uint8_t*)J.base;
+    b.strip_stride = J.strip_stride;
+    b.row_bytes = J.row_bytes;
+    b.p = (int16_t)p;
+    b.k = (int16_t)k;
+    b.op = (int16_t)cs.op;
+    b.x = (int16_t)cs.x;
+    b.y = (int16_t)cs.y;
+    pl->jobs.push_back(b);
+    const uint64_t strip = (uint64_t)(p - 1) * J.row_bytes;
+    const int moved = (cs.op == OP_P || cs.op == OP_Q || cs.op == OP_D) ? k + 1 : k + 2;
+    pl->bytes += (uint64_t)moved * strip;
+    pl->user_bytes += (uint64_t)k * strip;
+    pl->job_cost.push_back((uint64_t)moved * (p - 1));
+    if (p > pl->max_p) pl->max_p = p;
+    for (int j = 0; j < k + 2; ++j) {
+      const uintptr_t lo = (uintptr_t)J.base + (uintptr_t)j * J.strip_stride;
+      spans.push_back(Span{lo, lo + (uintptr_t)strip, (uint32_t)i});
+    }
+  }
+  std::sort(spans.begin(), spans.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+  uintptr_t reach = 0;
+  uint32_t reach_job = 0;
+  for (size_t i = 0; i < spans.size(); ++i) {
+    if (i > 0 && spans[i].lo < reach) {
+      const int rc = fail(RAID6C_E_ARG, "strips of jobs %u and %u overlap", reach_job, spans[i].job);
+      delete pl;
+      return rc;
+    }
+    if (spans[i].hi > reach) {
+      reach = spans[i].hi;
+      reach_job = spans[i].job;
+    }
+  }
+
+  (void)hipGetDevice(&pl->device);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) == hipSuccess && cus > 0)
+    pl->cus = cus;
+  pl->sched = raid6c_schedule{8, 4, RAID6C_ORDER_LARGEST_FIRST};
+  order_items(pl, pl->sched.order);
+  if (pl->items.size() > 0xFFFFFFFFull) {
+    delete pl;
+    return fail(RAID6C_E_ARG, "too many work items");
+  }
+
+  const size_t jb = std::max<size_t>(1, pl->jobs.size()) * sizeof(BatchJob);
+  const size_t ib = std::max<size_t>(1, pl->items.size()) * sizeof(BatchItem);
+  const size_t total = jb + ib + 256;
+  hipError_t e = hipMalloc(&pl->dmem, total);
+  if (e != hipSuccess) {
+    delete pl;
+    return fail(RAID6C_E_NOMEM, "hipMalloc of %zu bytes failed: %s", total, hipGetErrorString(e));
+  }
+  pl->args.jobs = (const BatchJob*)pl->dmem;
+  pl->args.items = (const BatchItem*)((uint8_t*)pl->dmem + jb);
+  pl->args.counter = (uint32_t*)((uint8_t*)pl->dmem + jb + ib);
+  pl->args.nitems = (uint32_t)pl->items.size();
+  if (!pl->jobs.empty() &&
+      (e = hipMemcpy((void*)pl->args.jobs, pl->jobs.data(), pl->jobs.size() * sizeof(BatchJob),
+                     hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(pl->dmem);
+    delete pl;
+    return fail(RAID6C_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
+  }
+  const int rc = build_graph(pl);
+  if (rc != RAID6C_OK) {
+    raid6c_plan_destroy(pl);
+    return rc;
+  }
+  *out = pl;
+  return RAID6C_OK;
+}
+
+int raid6c_plan_run(raid6c_plan* plan, void* stream) {
+  if (plan == nullptr) return fail(RAID6C_E_ARG, "plan is NULL");
+  if (plan->items.empty()) return RAID6C_OK;
+  const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAID6C_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+  return RAID6C_OK;
+}
+
+int raid6c_plan_get_schedule(const raid6c_plan* plan, raid6c_schedule* out) {
+  if (plan == nullptr || out == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
+  *out = plan->sched;
+  return RAID6C_OK;
+}
+
+int raid6c_plan_set_schedule(raid6c_plan* plan, const raid6c_schedule* s) {
+  if (plan == nullptr || s == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
+  if (!valid_schedule(*s)) return fail(RAID6C_E_ARG, "invalid schedule");
+  const bool reorder = s->order != plan->sched.order;
+  plan->sched = *s;
+  if (reorder) order_items(plan, s->order);
+  return build_graph(plan);
+}
+
+int raid6c_plan_stats(const raid6c_plan* plan, raid6c_plan_info* out) {
+  if (plan == nullptr || out == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
+  out->njobs = plan->jobs.size();
+  out->nitems = plan->items.size();
+  out->bytes_moved = plan->bytes;
+  out->user_bytes = plan->user_bytes;
+  out->max_p = plan->max_p;
+  out->grid = plan->cus * plan->sched.waves_per_cu;
+  return RAID6C_OK;
+}
+
+int raid6c_plan_autotune(raid6c_plan* plan, void* stream, int reps, float* best_ms) {
+  if (plan == nullptr) return fail(RAID6C_E_ARG, "plan is NULL");
+  if (reps < 1 || reps > 1000) return fail(RAID6C_E_ARG, "reps must be in [1, 1000]");
+  if (plan->items.empty()) {
+    if (best_ms) *best_ms = 0.f;
+    return RAID6C_OK;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(RAID6C_E_HIP, "hipEventCreate failed");
+  const int waves[] = {4, 8, 12, 16};
+  const int chunks[] = {1, 4, 16};
+  const int orders[] = {RAID6C_ORDER_LARGEST_FIRST, RAID6C_ORDER_BY_PRIME};
+  raid6c_schedule best = plan->sched;
+  float best_t = 1e30f;
+  int rc = RAID6C_OK;
+  for (int o : orders) {
+    for (int w : waves) {
+      for (int c : chunks) {
+        const raid6c_schedule cand{w, c, o};
+        if ((rc = raid6c_plan_set_schedule(plan, &cand)) != RAID6C_OK) goto done;
+        if ((rc = raid6c_plan_run(plan, stream)) != RAID6C_OK) goto done;  // warm-up
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r)
+          if ((rc = raid6c_plan_run(plan, stream)) != RAID6C_OK) goto done;
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(RAID6C_E_HIP, "hipEventSynchronize failed");
+          goto done;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (ms < best_t) {
+          best_t = ms;
+          best = cand;
+        }
+      }
+    }
+  }
+  rc = raid6c_plan_set_schedule(plan, &best);
+  if (best_ms) *best_ms = best_t;
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int raid6c_plan_destroy(raid6c_plan* plan) {
+  if (plan == nullptr) return RAID6C_OK;
+  free_graph(plan);
+  if (plan->dmem) (void)hipFree(plan->dmem);
+  delete plan;
+  return RAID6C_OK;
+}
+
+}  // extern "C"

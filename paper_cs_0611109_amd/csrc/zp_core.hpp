@@ -98,16 +98,35 @@ template <> struct bufio<4> {
   }
 };
 
-// Addresses of one stripe's strips for one thread's column.
-struct Cols {
+// Where one stripe's strips are, for one thread's column slice.  Two forms,
+// both offering strip(j) (a buffer resource over strip j), W() (row bytes)
+// and col (this thread's byte offset within a row):
+//  * ColsTable: a table of k+2 strip addresses (kernel argument) plus a
+//    per-stripe offset;
+//  * ColsStrided: strip j at base + j * strip_stride (batched jobs).
+struct ColsTable {
   const ZpArgs* a;
   uint64_t stripe_off;   // stripe * stripe_stride
-  uint32_t col;          // byte offset of this thread's slice within a row
+  uint32_t col;
   uint32_t strip_bytes;  // (p-1) * row_bytes
 
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t strip(int j) const {
     return make_rsrc(a->strip[j] + stripe_off, strip_bytes);
   }
+  __device__ __forceinline__ uint64_t W() const { return a->row_bytes; }
+};
+
+struct ColsStrided {
+  uint8_t* base;
+  uint64_t strip_stride;
+  uint32_t row_bytes;
+  uint32_t col;
+  uint32_t strip_bytes;
+
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t strip(int j) const {
+    return make_rsrc(base + (uint64_t)j * strip_stride, strip_bytes);
+  }
+  __device__ __forceinline__ uint64_t W() const { return row_bytes; }
 };
 
 template <typename VT>
@@ -133,15 +152,16 @@ __device__ __forceinline__ void rotate_up(VT (&aq)[P]) {
 // HP: accumulate acc_p; HQ: accumulate acc_q (Horner in C).  The strips are
 // taken U at a time: the U*(p-1) row loads of a batch are all issued before
 // the first of them is used, so each thread keeps U*(p-1) loads in flight.
-template <int P, int V, int U, bool HP, bool HQ>
-__device__ __forceinline__ void stream_data(const Cols& c, int k, int x, int y,
+template <int P, int V, int U, bool HP, bool HQ, class C>
+__device__ __forceinline__ void stream_data(const C& c, int k, int x, int y,
                                             typename vec_t<V>::type (&ap)[P - 1],
                                             typename vec_t<V>::type (&aq)[P]) {
   typedef typename vec_t<V>::type VT;
   constexpr int R = P - 1;
-  const uint64_t W = c.a->row_bytes;
+  const uint64_t W = c.W();
   int t = k - 1;
   for (; t >= U - 1; t -= U) {
+    __builtin_amdgcn_sched_barrier(0);
     VT v[U][R];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -168,6 +188,7 @@ __device__ __forceinline__ void stream_data(const Cols& c, int k, int x, int y,
   }
   for (; t >= 0; --t) {
     if (HQ) rotate_up<P>(aq);
+    __builtin_amdgcn_sched_barrier(0);
     if (t == x || t == y) continue;
     const __amdgpu_buffer_rsrc_t b = c.strip(t);
     VT v[R];
@@ -182,21 +203,21 @@ __device__ __forceinline__ void stream_data(const Cols& c, int k, int x, int y,
   }
 }
 
-template <int P, int V>
-__device__ __forceinline__ void load_into(const Cols& c, int j, typename vec_t<V>::type (&acc)[P - 1]) {
+template <int P, int V, class C>
+__device__ __forceinline__ void load_into(const C& c, int j, typename vec_t<V>::type (&acc)[P - 1]) {
   typedef typename vec_t<V>::type VT;
   const __amdgpu_buffer_rsrc_t b = c.strip(j);
-  const uint64_t W = c.a->row_bytes;
+  const uint64_t W = c.W();
 #pragma unroll
   for (int r = 0; r < P - 1; ++r) acc[r] = ld<VT>(b, r, W, c.col);
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int P, int V>
-__device__ __forceinline__ void xor_from(const Cols& c, int j, typename vec_t<V>::type (&acc)[P]) {
+template <int P, int V, class C>
+__device__ __forceinline__ void xor_from(const C& c, int j, typename vec_t<V>::type (&acc)[P]) {
   typedef typename vec_t<V>::type VT;
   const __amdgpu_buffer_rsrc_t b = c.strip(j);
-  const uint64_t W = c.a->row_bytes;
+  const uint64_t W = c.W();
   VT v[P - 1];
 #pragma unroll
   for (int r = 0; r < P - 1; ++r) v[r] = ld<VT>(b, r, W, c.col);
@@ -206,29 +227,29 @@ __device__ __forceinline__ void xor_from(const Cols& c, int j, typename vec_t<V>
   for (int r = 0; r < P - 1; ++r) acc[r] ^= v[r];
 }
 
-template <int P, int V>
-__device__ __forceinline__ void store_strip(const Cols& c, int j, const typename vec_t<V>::type (&v)[P - 1]) {
+template <int P, int V, class C>
+__device__ __forceinline__ void store_strip(const C& c, int j, const typename vec_t<V>::type (&v)[P - 1]) {
   typedef typename vec_t<V>::type VT;
   const __amdgpu_buffer_rsrc_t b = c.strip(j);
-  const uint64_t W = c.a->row_bytes;
+  const uint64_t W = c.W();
 #pragma unroll
   for (int r = 0; r < P - 1; ++r) st<VT>(b, r, W, c.col, v[r]);
 }
 
 // Q = reduction of acc_q from C to R_p: row r plus row p-1.
-template <int P, int V>
-__device__ __forceinline__ void store_reduced(const Cols& c, int j, const typename vec_t<V>::type (&aq)[P]) {
+template <int P, int V, class C>
+__device__ __forceinline__ void store_reduced(const C& c, int j, const typename vec_t<V>::type (&aq)[P]) {
   typedef typename vec_t<V>::type VT;
   const __amdgpu_buffer_rsrc_t b = c.strip(j);
-  const uint64_t W = c.a->row_bytes;
+  const uint64_t W = c.W();
   const VT top = aq[P - 1];
 #pragma unroll
   for (int r = 0; r < P - 1; ++r) st<VT>(b, r, W, c.col, aq[r] ^ top);
 }
 
 // Full encode of one tile: P and Q (either may be skipped).
-template <int P, int V, int U>
-__device__ __forceinline__ void tile_encode(const Cols& c, int k, bool wp, bool wq) {
+template <int P, int V, int U, class C>
+__device__ __forceinline__ void tile_encode(const C& c, int k, bool wp, bool wq) {
   typedef typename vec_t<V>::type VT;
   VT ap[P - 1], aq[P];
 #pragma unroll
@@ -248,8 +269,8 @@ __device__ __forceinline__ void tile_encode(const Cols& c, int k, bool wp, bool 
 
 // Recovery of one tile.  `lds` points at this thread's column of a region of
 // P rows with a row stride of `ls` vectors; only this thread touches it.
-template <int P, int V, int U>
-__device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& cs,
+template <int P, int V, int U, class C>
+__device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs,
                                              typename vec_t<V>::type* lds, int ls) {
   typedef typename vec_t<V>::type VT;
   constexpr int R = P - 1;
@@ -312,7 +333,7 @@ __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& c
     for (int u = 0; u < P; ++u) lds[u * ls] = aq[u];
     // (x^{p-x} a)[u] = a[(u + x) mod p], then reduce: row r plus row p-1.
     const __amdgpu_buffer_rsrc_t bx = c.strip(x), bp = c.strip(iP);
-    const uint64_t W = c.a->row_bytes;
+    const uint64_t W = c.W();
     const VT top = lds[(R + x) % P * ls];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -375,7 +396,7 @@ __device__ __forceinline__ void tile_recover(const Cols& c, int k, const Case& c
     }
   }
   const __amdgpu_buffer_rsrc_t bx = c.strip(cs.x), by = c.strip(cs.y);
-  const uint64_t W = c.a->row_bytes;
+  const uint64_t W = c.W();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const VT dy = lds[r * ls];

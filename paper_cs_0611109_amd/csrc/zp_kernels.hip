@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
   const uint32_t tile = blockIdx.x - stripe * a.tiles;
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
-  const Cols c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
+  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
   tile_encode<P, V, U>(c, a.k, true, true);
 }
 
@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   }
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
-  const Cols c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
+  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
   VT* lds = reinterpret_cast<VT*>(smem) + threadIdx.x;
   tile_recover<P, V, U>(c, a.k, cs, lds, (int)blockDim.x);
 }

@@ -141,3 +141,24 @@ def test_built_configurations():
             assert (m != 0) <= bool(r.raid6c_vec_mask(p) & v)
         v, u, t = r.raid6c_tune_get(p, 1, 1024)
         assert r.raid6c_unroll_mask(p, v) & u
+
+
+def test_plan_rejects_bad_jobs_before_device_work():
+    J = r.raid6c_job
+    good = J(0, 5, 4, -1, -1, 64, 256, FAKE)
+    cases = [
+        J(0, 9, 4, -1, -1, 64, 256, FAKE),            # not prime
+        J(0, 5, 6, -1, -1, 64, 256, FAKE),            # k > p
+        J(0, 5, 4, -1, -1, 24, 256, FAKE),            # row bytes
+        J(0, 5, 4, -1, -1, 64, 255, FAKE),            # stride
+        J(0, 5, 4, -1, -1, 64, 256, FAKE + 8),        # alignment
+        J(1, 5, 4, 2, 2, 64, 256, FAKE),              # equal erasures
+        J(1, 5, 4, -1, -1, 64, 256, FAKE),            # recover without erasure
+        J(3, 5, 4, -1, -1, 64, 256, FAKE),            # unknown op
+    ]
+    for bad in cases:
+        _err(r.raid6c_plan_create, [bad])
+        _err(r.raid6c_plan_create, [good, bad])
+    _err(r.raid6c_plan_create, [J(0, 67, 4, -1, -1, 64, 66 * 64, FAKE)], code=r.RAID6C_E_UNSUPPORTED)
+    # two jobs sharing bytes
+    _err(r.raid6c_plan_create, [J(0, 5, 4, -1, -1, 64, 256, FAKE), J(0, 5, 4, -1, -1, 64, 256, FAKE + 1024)])

@@ -1,0 +1,165 @@
+"""Full-size GPU runs of the benchmark geometries, in the launch
+configuration the library picks (the one bench.py times).
+
+Checks: sampled stripes against the CPU oracle (every 8th stripe), and, for
+recoveries, the property that every rebuilt strip equals the original, on all
+stripes.
+"""
+
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import datagen
+import paper_cs_0611109_amd as r
+from gpu_util import device, log
+from oracle import rs_gf256 as rs
+from oracle import zp_raid as zp
+
+pytestmark = pytest.mark.gpu
+
+
+def _fill(batch, seed, chunk=256):
+    import torch
+    p, k, w, n = batch.p, batch.k, batch.row_bytes, batch.nstripes
+    host = torch.empty((chunk, k, p - 1, w), dtype=torch.uint8).pin_memory()
+    for s0 in range(0, n, chunk):
+        c = min(chunk, n - s0)
+        datagen.fill_stripes(seed, s0, c, k, p, w, out=host.numpy()[:c], threads=16)
+        batch.tensor[s0:s0 + c, :k].copy_(host[:c])
+
+
+def _check_sample(batch, seed, step=8):
+    import torch
+    torch.cuda.synchronize()
+    p, k, w = batch.p, batch.k, batch.row_bytes
+    for s in range(0, batch.nstripes, step):
+        want = zp.encode_stripe(datagen.stripe_data(seed, s, k, p, w), p)
+        got = batch.tensor[s].cpu().numpy()
+        assert np.array_equal(got, want), s
+
+
+@pytest.mark.timeout(600)
+def test_config2_encode_and_rs_full_size():
+    import torch
+    device()
+    p, k, w, n = 13, 12, 4096, 4096
+    log(f"config2 p={p} k={k} W={w} stripes={n}")
+    b = r.StripeBatch.empty(p, k, w, n)
+    _fill(b, 2)
+    b.tensor[:, k:] = 0xA5
+    b.encode()
+    _check_sample(b, 2)
+    log("config2 RS GF(256) on the same bytes")
+    b.rs_encode()
+    torch.cuda.synchronize()
+    for s in range(0, n, 16):
+        data = datagen.stripe_data(2, s, k, p, w).reshape(k, -1)
+        P, Q = rs.encode(data)
+        got = b.tensor[s, k:].cpu().numpy().reshape(2, -1)
+        assert np.array_equal(got[0], P) and np.array_equal(got[1], Q), s
+
+
+@pytest.mark.timeout(600)
+def test_config3_recovery_full_size():
+    import torch
+    device()
+    p, k, w, n = 29, 28, 1024, 8192
+    log(f"config3 p={p} k={k} W={w} stripes={n}")
+    b = r.StripeBatch.empty(p, k, w, n)
+    _fill(b, 3)
+    b.encode()
+    _check_sample(b, 3, step=8)
+    orig = b.tensor.clone()
+    flat = b.tensor.view(n, k + 2, -1)
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    for kind in ("dd", "dp", "dq", "any"):
+        log(f"config3 recovery {kind}")
+        er = datagen.erasures(3, n, k, kind)
+        s_idx = torch.arange(n, device="cuda:0").repeat_interleave(2)
+        e_idx = torch.from_numpy(er.reshape(-1).astype(np.int64)).to("cuda:0")
+        flat[s_idx, e_idx] = 0x5A
+        b.recover(torch.from_numpy(er).to("cuda:0"), bad)
+        torch.cuda.synchronize()
+        assert int(bad.item()) == 0
+        assert torch.equal(b.tensor, orig), kind
+
+
+def _job_layout(jobs):
+    offs, pos = [], 0
+    for j in jobs:
+        offs.append(pos)
+        pos += (j.k + 2) * (j.p - 1) * j.row_bytes
+    return offs, pos
+
+
+@pytest.mark.timeout(900)
+def test_config4_batched_plan_full_size():
+    import torch
+    device()
+    n = 20000
+    jobs = datagen.batch_jobs(4, n)
+    offs, total = _job_layout(jobs)
+    log(f"config4: {n} stripes, {total / 1e9:.1f} GB")
+    buf = torch.empty(total, dtype=torch.uint8, device="cuda:0")
+    buf.fill_(0xA5)
+
+    def gen(i):
+        j = jobs[i]
+        return i, datagen.stripe_data(4, i, j.k, j.p, j.row_bytes)
+
+    with ThreadPoolExecutor(max_workers=16) as pool:
+        for s0 in range(0, n, 256):
+            for i, data in pool.map(gen, range(s0, min(n, s0 + 256))):
+                nb = data.size
+                buf[offs[i]:offs[i] + nb].copy_(torch.from_numpy(data.reshape(-1)))
+            if s0 % 4096 == 0:
+                log(f"config4: filled {s0} stripes")
+    base = buf.data_ptr()
+    # Recovery stripes are encoded beforehand by the plain path, then their
+    # erased strips are overwritten.
+    for i, j in enumerate(jobs):
+        if j.op == "recover":
+            strip = (j.p - 1) * j.row_bytes
+            r.raid6c_encode_n(j.p, j.k, j.row_bytes, base + offs[i], strip, (j.k + 2) * strip, 1)
+    torch.cuda.synchronize()
+    for i, j in enumerate(jobs):
+        if j.op == "recover":
+            strip = (j.p - 1) * j.row_bytes
+            for e in (j.e0, j.e1):
+                buf[offs[i] + e * strip: offs[i] + (e + 1) * strip].fill_(0x3C)
+    plan_jobs = []
+    for i, j in enumerate(jobs):
+        strip = (j.p - 1) * j.row_bytes
+        op = r.RAID6C_JOB_ENCODE if j.op == "encode" else r.RAID6C_JOB_RECOVER
+        plan_jobs.append(r.raid6c_job(op, j.p, j.k, j.e0, j.e1, j.row_bytes, strip, base + offs[i]))
+    plan = r.raid6c_plan_create(plan_jobs)
+    try:
+        log("config4: autotune + run")
+        r.raid6c_plan_autotune(plan, reps=1)
+        r.raid6c_plan_run(plan)
+        torch.cuda.synchronize()
+    finally:
+        r.raid6c_plan_destroy(plan)
+    # every 8th stripe, and at least 8 stripes of every (p, op) class
+    seen = {}
+    sample = []
+    for i, j in enumerate(jobs):
+        key = (j.p, j.op)
+        if i % 8 == 0 or seen.get(key, 0) < 8:
+            sample.append(i)
+            seen[key] = seen.get(key, 0) + 1
+    log(f"config4: checking {len(sample)} stripes against the oracle")
+
+    def check(i):
+        j = jobs[i]
+        want = zp.encode_stripe(datagen.stripe_data(4, i, j.k, j.p, j.row_bytes), j.p)
+        return i, want
+
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        for i, want in pool.map(check, sample):
+            j = jobs[i]
+            nb = want.size
+            got = buf[offs[i]:offs[i] + nb].cpu().numpy().reshape(want.shape)
+            assert np.array_equal(got, want), (i, j)
