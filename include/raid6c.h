@@ -229,6 +229,13 @@ int raid6c_plan_autotune(raid6c_plan* plan, void* stream, int reps, float* best_
 /* Free the plan and its device memory (NULL is allowed). */
 int raid6c_plan_destroy(raid6c_plan* plan);
 
+/* Run every job as its own plain launch (raid6c_encode_n with one stripe,
+ * raid6c_recover_1 or raid6c_recover_2), in order, on `stream`: the
+ * per-request path that plans replace.  Jobs are checked as by
+ * raid6c_plan_create (except for overlap); on an invalid job nothing is
+ * launched.  Errors: as raid6c_plan_create. */
+int raid6c_run_jobs(const raid6c_job* jobs, size_t njobs, void* stream);
+
 /* ------------------------------------------------------------------------
  * Launch configuration (used by the autotuner and by tests)
  *
@@ -260,6 +267,19 @@ int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int*
 
 /* Forget every recorded configuration (back to the built-in rule). */
 void raid6c_tune_clear(void);
+
+/* Autotuner for the strided entry points: run every built (vec, unroll,
+ * threads) configuration on the caller's stripes -- op 0: raid6c_encode_n,
+ * op 1: raid6c_recover_n with `erasures` (device, as there) -- once to warm
+ * up and `reps` times timed with HIP events on `stream`, then record the
+ * fastest for (p, op, row-size bucket) and return its mean time per launch
+ * in *best_ms (may be NULL).  Every run rewrites the same output bytes.
+ * Synchronises.  Errors: as raid6c_encode_n / raid6c_recover_n, plus
+ * RAID6C_E_ARG for op not 0/1 or reps outside 1..1000, RAID6C_E_HIP. */
+int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base,
+                      size_t strip_stride, size_t stripe_stride, size_t nstripes,
+                      int op, const int32_t* erasures, int reps, void* stream,
+                      float* best_ms);
 
 #ifdef __cplusplus
 }

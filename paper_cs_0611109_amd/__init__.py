@@ -21,6 +21,7 @@ from ._lib import (  # noqa: F401
     raid6c_plan_run,
     raid6c_plan_set_schedule,
     raid6c_plan_stats,
+    raid6c_run_jobs,
     raid6c_schedule,
     RAID6C_E_ARG,
     RAID6C_E_HIP,
@@ -30,6 +31,7 @@ from ._lib import (  # noqa: F401
     RAID6C_OK,
     Raid6cError,
     load,
+    raid6c_autotune_n,
     raid6c_encode,
     raid6c_encode_n,
     raid6c_is_supported_prime,

@@ -42,6 +42,8 @@ SIGNATURES = {
     "raid6c_tune_get": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
                                  ctypes.POINTER(_c_int)]),
     "raid6c_tune_clear": (None, []),
+    "raid6c_autotune_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _c_int, _vp, _c_int,
+                                   _vp, ctypes.POINTER(ctypes.c_float)]),
     "raid6c_plan_create": (_c_int, [_vp, _c_size, _vp]),
     "raid6c_plan_run": (_c_int, [_vp, _vp]),
     "raid6c_plan_get_schedule": (_c_int, [_vp, _vp]),
@@ -49,6 +51,7 @@ SIGNATURES = {
     "raid6c_plan_stats": (_c_int, [_vp, _vp]),
     "raid6c_plan_autotune": (_c_int, [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_float)]),
     "raid6c_plan_destroy": (_c_int, [_vp]),
+    "raid6c_run_jobs": (_c_int, [_vp, _c_size, _vp]),
 }
 
 
@@ -248,3 +251,18 @@ def raid6c_plan_autotune(plan, stream=None, reps=3) -> float:
 
 def raid6c_plan_destroy(plan):
     return _check(load().raid6c_plan_destroy(plan))
+
+
+def raid6c_run_jobs(jobs, stream=None):
+    """Every job as its own plain launch (the per-request path)."""
+    arr = jobs if isinstance(jobs, ctypes.Array) else (raid6c_job * len(jobs))(*jobs)
+    return _check(load().raid6c_run_jobs(ctypes.cast(arr, _vp) if len(arr) else None, len(arr), _stream(stream)))
+
+
+def raid6c_autotune_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, op, erasures=None, reps=5,
+                      stream=None) -> float:
+    """Pick and record the fastest launch configuration; returns its ms per launch."""
+    ms = ctypes.c_float()
+    _check(load().raid6c_autotune_n(p, k, row_bytes, _ptr(base), strip_stride, stripe_stride, nstripes, op,
+                                    _ptr(erasures), reps, _stream(stream), ctypes.byref(ms)))
+    return ms.value

@@ -211,6 +211,29 @@ int build_graph(raid6c_plan* pl) {
   return RAID6C_OK;
 }
 
+int check_job(const raid6c_job& J, size_t i, Case* out) {
+  const int p = J.p, k = J.k;
+  if (!is_odd_prime(p)) return fail(RAID6C_E_ARG, "job %zu: p = %d is not an odd prime", i, p);
+  if (p > kMaxPrime) return fail(RAID6C_E_UNSUPPORTED, "job %zu: p = %d is not built", i, p);
+  if (k < 1 || k > p) return fail(RAID6C_E_ARG, "job %zu: k = %d not in [1, %d]", i, k, p);
+  if (J.row_bytes == 0 || (J.row_bytes % 16) != 0)
+    return fail(RAID6C_E_ARG, "job %zu: row_bytes must be a positive multiple of 16", i);
+  if ((uint64_t)(p - 1) * J.row_bytes >= (1ull << 31)) return fail(RAID6C_E_ARG, "job %zu: strip of 2 GiB or more", i);
+  if (J.base == nullptr || ((uintptr_t)J.base & 15u) != 0)
+    return fail(RAID6C_E_ARG, "job %zu: base is NULL or not 16-byte aligned", i);
+  if ((J.strip_stride % 16) != 0 || J.strip_stride < (uint64_t)(p - 1) * J.row_bytes)
+    return fail(RAID6C_E_ARG, "job %zu: bad strip_stride", i);
+  if (J.op != RAID6C_JOB_ENCODE && J.op != RAID6C_JOB_RECOVER)
+    return fail(RAID6C_E_ARG, "job %zu: op must be encode or recover", i);
+  Case cs{OP_PQ, -1, -1};
+  if (J.op == RAID6C_JOB_RECOVER) {
+    cs = classify(k, J.e0, J.e1);
+    if (cs.op == OP_BAD) return fail(RAID6C_E_ARG, "job %zu: invalid erasures (%d, %d)", i, J.e0, J.e1);
+  }
+  *out = cs;
+  return RAID6C_OK;
+}
+
 bool valid_schedule(const raid6c_schedule& s) {
   return s.waves_per_cu >= 1 && s.waves_per_cu <= 32 && s.chunk >= 1 && s.chunk <= 1024 &&
          (s.order == RAID6C_ORDER_LARGEST_FIRST || s.order == RAID6C_ORDER_BY_PRIME ||
@@ -239,25 +262,8 @@ int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) 
   for (size_t i = 0; i < njobs; ++i) {
     const raid6c_job& J = jobs[i];
     const int p = J.p, k = J.k;
-    int rc = RAID6C_OK;
-    if (!is_odd_prime(p)) rc = fail(RAID6C_E_ARG, "job %zu: p = %d is not an odd prime", i, p);
-    else if (p > kMaxPrime) rc = fail(RAID6C_E_UNSUPPORTED, "job %zu: p = %d is not built", i, p);
-    else if (k < 1 || k > p) rc = fail(RAID6C_E_ARG, "job %zu: k = %d not in [1, %d]", i, k, p);
-    else if (J.row_bytes == 0 || (J.row_bytes % 16) != 0)
-      rc = fail(RAID6C_E_ARG, "job %zu: row_bytes must be a positive multiple of 16", i);
-    else if ((uint64_t)(p - 1) * J.row_bytes >= (1ull << 31))
-      rc = fail(RAID6C_E_ARG, "job %zu: strip of 2 GiB or more", i);
-    else if (J.base == nullptr || ((uintptr_t)J.base & 15u) != 0)
-      rc = fail(RAID6C_E_ARG, "job %zu: base is NULL or not 16-byte aligned", i);
-    else if ((J.strip_stride % 16) != 0 || J.strip_stride < (uint64_t)(p - 1) * J.row_bytes)
-      rc = fail(RAID6C_E_ARG, "job %zu: bad strip_stride", i);
-    else if (J.op != RAID6C_JOB_ENCODE && J.op != RAID6C_JOB_RECOVER)
-      rc = fail(RAID6C_E_ARG, "job %zu: op must be encode or recover", i);
     Case cs{OP_PQ, -1, -1};
-    if (rc == RAID6C_OK && J.op == RAID6C_JOB_RECOVER) {
-      cs = classify(k, J.e0, J.e1);
-      if (cs.op == OP_BAD) rc = fail(RAID6C_E_ARG, "job %zu: invalid erasures (%d, %d)", i, J.e0, J.e1);
-    }
+    const int rc = check_job(J, i, &cs);
     if (rc != RAID6C_OK) {
       delete pl;
       return rc;
@@ -418,6 +424,30 @@ done:
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;
+}
+
+int raid6c_run_jobs(const raid6c_job* jobs, size_t njobs, void* stream) {
+  if (jobs == nullptr && njobs != 0) return fail(RAID6C_E_ARG, "jobs is NULL");
+  for (size_t i = 0; i < njobs; ++i) {
+    Case cs;
+    const int rc = check_job(jobs[i], i, &cs);
+    if (rc != RAID6C_OK) return rc;
+  }
+  for (size_t i = 0; i < njobs; ++i) {
+    const raid6c_job& J = jobs[i];
+    int rc;
+    if (J.op == RAID6C_JOB_ENCODE) {
+      rc = raid6c_encode_n(J.p, J.k, J.row_bytes, J.base, J.strip_stride, (size_t)(J.k + 2) * J.strip_stride, 1,
+                           stream);
+    } else {
+      void* strips[kMaxStrips];
+      for (int j = 0; j < J.k + 2; ++j) strips[j] = (uint8_t*)J.base + (size_t)j * J.strip_stride;
+      rc = (J.e1 < 0) ? raid6c_recover_1(J.p, J.k, J.row_bytes, strips, J.e0, stream)
+                      : raid6c_recover_2(J.p, J.k, J.row_bytes, strips, J.e0, J.e1, stream);
+    }
+    if (rc != RAID6C_OK) return rc;
+  }
+  return RAID6C_OK;
 }
 
 int raid6c_plan_destroy(raid6c_plan* plan) {

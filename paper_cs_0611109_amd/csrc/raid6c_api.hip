@@ -321,4 +321,64 @@ int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int*
 
 void raid6c_tune_clear(void) { clear_tuned(); }
 
+int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                      size_t nstripes, int op, const int32_t* erasures, int reps, void* stream, float* best_ms) {
+  g_last_error.clear();
+  if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
+  if (reps < 1 || reps > 1000) return fail(RAID6C_E_ARG, "reps must be in [1, 1000]");
+  int rc = check_strided(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes);
+  if (rc != RAID6C_OK) return rc;
+  if (op == 1 && (erasures == nullptr || ((uintptr_t)erasures & 3u) != 0))
+    return fail(RAID6C_E_ARG, "erasures is NULL or not 4-byte aligned");
+  const ZpPrimeEntry* e = zp_prime_entry(p);
+  if (e == nullptr) return fail(RAID6C_E_UNSUPPORTED, "p = %d is not built", p);
+  if (nstripes == 0) {
+    if (best_ms) *best_ms = 0.f;
+    return RAID6C_OK;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(RAID6C_E_HIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(RAID6C_E_HIP, "hipEventCreate failed");
+  }
+  const ZpKind kind = op == 0 ? KIND_ENCODE : KIND_RECOVER;
+  const int bucket = row_bucket(row_bytes);
+  ZpArgs a = strided_args(k, row_bytes, base, strip_stride, stripe_stride);
+  a.erasures = op == 1 ? erasures : nullptr;
+  ZpConfig best{0, 0, 0};
+  float best_t = 1e30f;
+  for (int vec = 1; vec <= 4 && rc == RAID6C_OK; vec *= 2) {
+    for (int unroll = 1; unroll <= 4 && rc == RAID6C_OK; unroll *= 2) {
+      if (!e->has(vec, unroll)) continue;
+      for (int threads = 64; threads <= 256 && rc == RAID6C_OK; threads *= 2) {
+        set_tuned(p, kind, bucket, ZpConfig{vec, unroll, threads});
+        if ((rc = launch_zp(p, kind, a, nstripes, stream)) != RAID6C_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && rc == RAID6C_OK; ++r) rc = launch_zp(p, kind, a, nstripes, stream);
+        (void)hipEventRecord(e1, s);
+        if (rc != RAID6C_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(RAID6C_E_HIP, "hipEventSynchronize failed");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (ms < best_t) {
+          best_t = ms;
+          best = ZpConfig{vec, unroll, threads};
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != RAID6C_OK) return rc;
+  set_tuned(p, kind, bucket, best);
+  if (best_ms) *best_ms = best_t;
+  return RAID6C_OK;
+}
+
 }  // extern "C"

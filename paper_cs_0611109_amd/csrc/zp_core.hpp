@@ -93,8 +93,17 @@ template <> struct bufio<4> {
   static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, RAID6C_LOAD_POLICY);
   }
+  // Stored as two 8-byte halves.  A buffer store of more than 8 bytes whose
+  // data registers are rewritten by the very next vector ALU instructions
+  // needs a wait state that the compiler does not insert when the store's
+  // offset comes from a scalar register; on gfx950 that produced wrong bytes
+  // in the last dword of a few lanes.  8-byte stores are not affected.
   static __device__ __forceinline__ void store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, RAID6C_STORE_POLICY);
+    typedef vec_t<2>::type H;
+    // The halves use different scalar offsets so that they are not merged
+    // back into one 16-byte store.
+    __builtin_amdgcn_raw_buffer_store_b64(H{v.x, v.y}, r, voff, soff, RAID6C_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b64(H{v.z, v.w}, r, voff, soff + 8u, RAID6C_STORE_POLICY);
   }
 };
 
@@ -270,11 +279,15 @@ __device__ __forceinline__ void tile_encode(const C& c, int k, bool wp, bool wq)
 // Recovery of one tile.  `lds` points at this thread's column of a region of
 // P rows with a row stride of `ls` vectors; only this thread touches it.
 template <int P, int V, int U, class C>
-__device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs,
+__device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_in,
                                              typename vec_t<V>::type* lds, int ls) {
   typedef typename vec_t<V>::type VT;
   constexpr int R = P - 1;
   const int iP = k, iQ = k + 1;
+  // The case is uniform over the wave; keep it (and every strip address
+  // derived from it) in scalar registers.
+  const Case cs{__builtin_amdgcn_readfirstlane(cs_in.op), __builtin_amdgcn_readfirstlane(cs_in.x),
+                __builtin_amdgcn_readfirstlane(cs_in.y)};
 
   switch (cs.op) {
     case OP_PQ:

@@ -45,8 +45,10 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   const uint32_t tile = blockIdx.x - stripe * a.tiles;
   int e0 = a.e0, e1 = a.e1;
   if (a.erasures != nullptr) {
-    e0 = a.erasures[2 * (uint64_t)stripe];
-    e1 = a.erasures[2 * (uint64_t)stripe + 1];
+    // One stripe per work-group: the entry is uniform.  Saying so keeps the
+    // strip addresses derived from it in scalar registers.
+    e0 = __builtin_amdgcn_readfirstlane(a.erasures[2 * (uint64_t)stripe]);
+    e1 = __builtin_amdgcn_readfirstlane(a.erasures[2 * (uint64_t)stripe + 1]);
   }
   const Case cs = classify(a.k, e0, e1);
   if (cs.op == OP_BAD) {

@@ -214,3 +214,22 @@ def test_rs_encode_matches_oracle():
         got = to_host(dev)
         assert np.array_equal(got[:, k], P) and np.array_equal(got[:, k + 1], Q)
         assert np.array_equal(got[:, :k], data)
+
+
+@pytest.mark.parametrize("p,w", [(5, 4096), (13, 4096), (29, 1024)])
+def test_every_config_every_two_erasure_kind_many_stripes(p, w):
+    # Many stripes per (configuration, case): a fault that hits a few lanes of
+    # a few work-groups shows up here even when small tests pass.
+    k = p - 1
+    n = 192
+    want = zp.encode_stripe(datagen.fill_stripes(p, 0, n, k, p, w), p)
+    for (v, u, t) in _configs(p):
+        r.raid6c_tune_set(p, 0, w, v, u, t)
+        r.raid6c_tune_set(p, 1, w, v, u, t)
+        log(f"many stripes p={p} W={w} vec={v} unroll={u} threads={t}")
+        assert np.array_equal(_encode_on_gpu(want, p, k, w), want), ("encode", v, u, t)
+        for kind in ("dd", "dp", "dq", "pq", "d"):
+            er = datagen.erasures(p * 100 + v + u + t, n, k, kind)
+            got = _recover_on_gpu(want, p, k, w, er)
+            bad = [s for s in range(n) if not np.array_equal(got[s], want[s])]
+            assert not bad, (kind, v, u, t, bad[:5], [tuple(er[s]) for s in bad[:5]])
