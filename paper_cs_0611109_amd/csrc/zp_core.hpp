@@ -276,12 +276,26 @@ __device__ __forceinline__ void tile_encode(const C& c, int k, bool wp, bool wq)
   if (wq) store_reduced<P, V>(c, k + 1, aq);
 }
 
-// Recovery of one tile.  `lds` points at this thread's column of a region of
-// P rows with a row stride of `ls` vectors; only this thread touches it.
-template <int P, int V, int U, class C>
-__device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_in,
-                                             typename vec_t<V>::type* lds, int ls) {
+// Component c of a vector (a dword column of the thread's slice).
+template <int V> struct comp;
+template <> struct comp<1> {
+  static __device__ __forceinline__ uint32_t get(uint32_t v, int) { return v; }
+  static __device__ __forceinline__ void set(uint32_t& v, int, uint32_t x) { v = x; }
+};
+template <int V> struct comp {
   typedef typename vec_t<V>::type VT;
+  static __device__ __forceinline__ uint32_t get(const VT& v, int c) { return v[c]; }
+  static __device__ __forceinline__ void set(VT& v, int c, uint32_t x) { v[c] = x; }
+};
+
+// Recovery of one tile.  `lds` points at this thread's column of a region of
+// P rows of one dword, row stride `ls` dwords; only this thread touches it.
+// The data-dependent row permutations are done one dword column at a time,
+// so the region does not grow with the vector width.
+template <int P, int V, int U, class C>
+__device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_in, uint32_t* lds, int ls) {
+  typedef typename vec_t<V>::type VT;
+  typedef comp<V> CP;
   constexpr int R = P - 1;
   const int iP = k, iQ = k + 1;
   // The case is uniform over the wave; keep it (and every strip address
@@ -321,14 +335,17 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
     load_into<P, V>(c, iP, ap);
     stream_data<P, V, U, true, true>(c, k, x, -1, ap, aq);
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[r * ls] = ap[r];
-    lds[R * ls] = (VT)(0u);
-    // (x^x D~)[u] = D~[(u - x) mod p]
+    for (int cc = 0; cc < V; ++cc) {
 #pragma unroll
-    for (int u = 0; u < P; ++u) {
-      int w = u - x;
-      if (w < 0) w += P;
-      aq[u] ^= lds[w * ls];
+      for (int r = 0; r < R; ++r) lds[r * ls] = CP::get(ap[r], cc);
+      lds[R * ls] = 0u;
+      // (x^x D~)[u] = D~[(u - x) mod p]
+#pragma unroll
+      for (int u = 0; u < P; ++u) {
+        int w = u - x;
+        if (w < 0) w += P;
+        CP::set(aq[u], cc, CP::get(aq[u], cc) ^ lds[w * ls]);
+      }
     }
     store_strip<P, V>(c, x, ap);
     store_reduced<P, V>(c, iQ, aq);
@@ -342,17 +359,24 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
     for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
     stream_data<P, V, U, true, true>(c, k, x, -1, ap, aq);
     xor_from<P, V>(c, iQ, aq);
+    // (x^{p-x} a)[u] = a[(u + x) mod p], in place.
 #pragma unroll
-    for (int u = 0; u < P; ++u) lds[u * ls] = aq[u];
-    // (x^{p-x} a)[u] = a[(u + x) mod p], then reduce: row r plus row p-1.
+    for (int cc = 0; cc < V; ++cc) {
+#pragma unroll
+      for (int u = 0; u < P; ++u) lds[u * ls] = CP::get(aq[u], cc);
+#pragma unroll
+      for (int u = 0; u < P; ++u) {
+        int w = u + x;
+        if (w >= P) w -= P;
+        CP::set(aq[u], cc, lds[w * ls]);
+      }
+    }
+    // Reduce (row r plus row p-1), store D_x, then P = (data sum) + D_x.
     const __amdgpu_buffer_rsrc_t bx = c.strip(x), bp = c.strip(iP);
     const uint64_t W = c.W();
-    const VT top = lds[(R + x) % P * ls];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      int w = r + x;
-      if (w >= P) w -= P;
-      const VT d = lds[w * ls] ^ top;
+      const VT d = aq[r] ^ aq[R];
       st<VT>(bx, r, W, c.col, d);
       st<VT>(bp, r, W, c.col, d ^ ap[r]);
     }
@@ -368,53 +392,54 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
   stream_data<P, V, U, true, true>(c, k, cs.x, cs.y, ap, aq);
   xor_from<P, V>(c, iQ, aq);
 
-  // T~[u] = dP~[u] + dQ~[(u + x) mod p], built in natural row order through
-  // LDS (aq is reused for T~), then written back for the chain.
 #pragma unroll
-  for (int u = 0; u < P; ++u) lds[u * ls] = aq[u];
+  for (int cc = 0; cc < V; ++cc) {
+    // T~[u] = dP~[u] + dQ~[(u + x) mod p], built in aq (natural row order).
 #pragma unroll
-  for (int u = 0; u < P; ++u) {
-    int w = u + x;
-    if (w >= P) w -= P;
-    aq[u] = lds[w * ls];
-  }
+    for (int u = 0; u < P; ++u) lds[u * ls] = CP::get(aq[u], cc);
+    uint32_t e = 0u;  // XOR of all p rows of T~
 #pragma unroll
-  for (int r = 0; r < R; ++r) aq[r] ^= ap[r];
-  // e = XOR of all p rows of T~.
-  VT e = (VT)(0u);
-#pragma unroll
-  for (int u = 0; u < P; ++u) e ^= aq[u];
-#pragma unroll
-  for (int u = 0; u < P; ++u) lds[u * ls] = aq[u];
-
-  // Chain over rows u_s = (p-1 + s z) mod p, s = 1..p-1:
-  // D~[u_s] = T~[u_s] + e + D~[u_{s-1}], D~[p-1] = 0, written in place (each
-  // row is visited once, so its T~ value is consumed before it is replaced).
-  // The next row's value is read before the current one is written: rows of
-  // consecutive steps differ, so the read does not see the write.
-  {
-    int u = R + z;
-    if (u >= P) u -= P;
-    VT t = lds[u * ls];
-    VT d = (VT)(0u);
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      int un = u + z;
-      if (un >= P) un -= P;
-      const VT tn = (s + 1 < R) ? lds[un * ls] : (VT)(0u);
-      d = t ^ e ^ d;
-      lds[u * ls] = d;
-      t = tn;
-      u = un;
+    for (int u = 0; u < P; ++u) {
+      int w = u + x;
+      if (w >= P) w -= P;
+      uint32_t t = lds[w * ls];
+      if (u < R) t ^= CP::get(ap[u], cc);
+      e ^= t;
+      CP::set(aq[u], cc, t);
     }
+#pragma unroll
+    for (int u = 0; u < P; ++u) lds[u * ls] = CP::get(aq[u], cc);
+    // Chain over rows u_s = (p-1 + s z) mod p, s = 1..p-1:
+    // D~[u_s] = T~[u_s] + e + D~[u_{s-1}], D~[p-1] = 0, written in place (each
+    // row is visited once, so its T~ value is read before it is replaced).
+    // The next row's value is read before the current one is written: rows
+    // of consecutive steps differ, so the read does not see the write.
+    {
+      int u = R + z;
+      if (u >= P) u -= P;
+      uint32_t t = lds[u * ls];
+      uint32_t d = 0u;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        int un = u + z;
+        if (un >= P) un -= P;
+        const uint32_t tn = (s + 1 < R) ? lds[un * ls] : 0u;
+        d = t ^ e ^ d;
+        lds[u * ls] = d;
+        t = tn;
+        u = un;
+      }
+    }
+    // D_y in natural row order back into aq.
+#pragma unroll
+    for (int r = 0; r < R; ++r) CP::set(aq[r], cc, lds[r * ls]);
   }
   const __amdgpu_buffer_rsrc_t bx = c.strip(cs.x), by = c.strip(cs.y);
   const uint64_t W = c.W();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const VT dy = lds[r * ls];
-    st<VT>(by, r, W, c.col, dy);
-    st<VT>(bx, r, W, c.col, dy ^ ap[r]);
+    st<VT>(by, r, W, c.col, aq[r]);
+    st<VT>(bx, r, W, c.col, aq[r] ^ ap[r]);
   }
 }
 

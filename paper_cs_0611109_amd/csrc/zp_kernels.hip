@@ -40,7 +40,6 @@ __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
 template <int P, int V, int U>
 __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  typedef typename vec_t<V>::type VT;
   const uint32_t stripe = blockIdx.x / a.tiles;
   const uint32_t tile = blockIdx.x - stripe * a.tiles;
   int e0 = a.e0, e1 = a.e1;
@@ -58,7 +57,7 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
   const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
-  VT* lds = reinterpret_cast<VT*>(smem) + threadIdx.x;
+  uint32_t* lds = reinterpret_cast<uint32_t*>(smem) + threadIdx.x;
   tile_recover<P, V, U>(c, a.k, cs, lds, (int)blockDim.x);
 }
 
@@ -84,7 +83,7 @@ hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t
     if (kind == KIND_ENCODE) {
       hipLaunchKernelGGL((zp_encode_kernel<kP, V, U>), g, b, 0, stream, a);
     } else {
-      const size_t lds = (size_t)kP * cfg.threads * V * 4;
+      const size_t lds = (size_t)kP * cfg.threads * 4;
       hipLaunchKernelGGL((zp_recover_kernel<kP, V, U>), g, b, lds, stream, a);
     }
     return hipGetLastError();
