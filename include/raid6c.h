@@ -130,6 +130,32 @@ int raid6c_recover_n(int p, int k, size_t row_bytes, void* base,
                      const int32_t* erasures, int32_t* bad_count, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Write path and degraded read of one stripe
+ * ------------------------------------------------------------------------ */
+
+/* Write a stripe from a payload: data strip t is read from
+ * src + t*src_strip_stride, stored to strips[t], and P and Q (strips[k],
+ * strips[k+1]) are computed from it in the same pass (Corollary 3.2.4).
+ *   src    : device payload, k strips of (p-1)*row_bytes bytes (read only);
+ *            src_strip_stride a multiple of 16, >= (p-1)*row_bytes
+ *   strips : host array of k+2 device pointers (written)
+ * The payload must not overlap the stripe.  Errors: as raid6c_encode, plus
+ * RAID6C_E_ARG for a NULL or misaligned source or a bad stride. */
+int raid6c_write(int p, int k, size_t row_bytes, const void* src, size_t src_strip_stride,
+                 void* const* strips, void* stream);
+
+/* Degraded read: rebuild the erased strip(s) e0 (and e1 unless -1) of a
+ * stripe into `out` without writing the stripe (Lemma 3.1.2 as in
+ * raid6c_recover_1 / raid6c_recover_2).  `out` receives the rebuilt strips
+ * in ascending strip order, each (p-1)*row_bytes bytes, contiguous.
+ *   strips : host array of k+2 device pointers; only the surviving strips
+ *            are read, the erased entries may be NULL.
+ * Errors: as raid6c_recover_2 (or raid6c_recover_1 when e1 = -1), plus
+ * RAID6C_E_ARG for a NULL or misaligned `out` or one overlapping a strip. */
+int raid6c_read_degraded(int p, int k, size_t row_bytes, const void* const* strips, int e0, int e1,
+                         void* out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Comparison code: Reed-Solomon P+Q over GF(256), polynomial 0x11D
  * ------------------------------------------------------------------------ */
 
@@ -235,6 +261,115 @@ int raid6c_plan_destroy(raid6c_plan* plan);
  * raid6c_plan_create (except for overlap); on an invalid job nothing is
  * launched.  Errors: as raid6c_plan_create. */
 int raid6c_run_jobs(const raid6c_job* jobs, size_t njobs, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of writes and degraded reads
+ *
+ * The server owns a stripe store of `store_bytes` of device memory (its HBM
+ * budget), used as a ring in arrival order; a write that needs room evicts
+ * the oldest stripes that no admitted request is using, and waits while the
+ * oldest one is busy.  A scheduler thread admits pending requests into free
+ * slots (up to max_inflight batches on their own streams, max_batch requests
+ * each) and launches each batch as one persistent kernel; requests arriving
+ * meanwhile go into the next free slot, so batches overlap on the device.  A
+ * completion thread reports each request with its arrival, launch and
+ * completion times (ns on the server's steady clock).  With `plain` set,
+ * every request is one plain launch (raid6c_write / raid6c_read_degraded)
+ * on a single stream instead: the per-request path, for comparison.
+ * Results are bit-identical either way.
+ * ------------------------------------------------------------------------ */
+
+#define RAID6C_REQ_WRITE 0  /* payload -> new resident stripe (data + P + Q) */
+#define RAID6C_REQ_READ  1  /* rebuild erased strip(s) of a resident stripe into dst */
+
+#define RAID6C_ST_OK            0
+#define RAID6C_ST_NOT_RESIDENT  1  /* read of an unknown or evicted stripe */
+#define RAID6C_ST_TOO_LARGE     2  /* stripe larger than the whole store */
+#define RAID6C_ST_INVALID       3  /* bad geometry, erasures or buffers */
+#define RAID6C_ST_DUPLICATE     4  /* write of a stripe id that is resident */
+
+/* A write gives p, k, row_bytes, a new stripe_id and `src`: the device
+ * payload, k strips of (p-1)*row_bytes bytes back to back, which must stay
+ * valid until the request completes.  A read gives the stripe_id, the erased
+ * strips e0 and e1 (-1 for one) and `dst`: a device buffer, not overlapping
+ * the store, that receives the rebuilt strips in ascending strip order.
+ * `tag` is returned with the completion. */
+typedef struct raid6c_request {
+  int32_t kind;
+  int32_t p;
+  int32_t k;
+  int32_t e0;
+  int32_t e1;
+  uint32_t row_bytes;
+  uint64_t stripe_id;
+  const void* src;
+  void* dst;
+  uint64_t tag;
+} raid6c_request;
+
+typedef struct raid6c_completion {
+  uint64_t tag;
+  int32_t status;       /* RAID6C_ST_* */
+  int32_t batch_size;   /* requests launched together with this one */
+  uint64_t arrival_ns;  /* submission (or scheduled arrival in a replay) */
+  uint64_t launch_ns;
+  uint64_t complete_ns;
+} raid6c_completion;
+
+typedef struct raid6c_server_config {
+  uint64_t store_bytes;  /* HBM budget of the stripe store, >= 4096 */
+  int32_t max_inflight;  /* batches in flight, 1..64 */
+  int32_t max_batch;     /* requests per batch, 1..65536 */
+  int32_t plain;         /* 1: one plain launch per request on one stream */
+  int32_t waves_per_cu;  /* persistent work-groups per compute unit (0 = 8) */
+} raid6c_server_config;
+
+typedef struct raid6c_server_stats {
+  uint64_t submitted;
+  uint64_t completed;
+  uint64_t batches;
+  uint64_t evictions;
+  uint64_t user_bytes;   /* k*(p-1)*row_bytes of every successful request */
+  uint64_t resident;     /* stripes in the store */
+  uint64_t store_used;   /* bytes they occupy */
+} raid6c_server_stats;
+
+typedef struct raid6c_server raid6c_server;
+
+/* Create a server on the current device (allocates the store, streams and
+ * two host threads).  Errors: RAID6C_E_ARG, RAID6C_E_NOMEM, RAID6C_E_HIP. */
+int raid6c_server_create(const raid6c_server_config* cfg, raid6c_server** out);
+
+/* Queue requests (thread-safe); their arrival time is now.  Bad requests
+ * complete with a status, not an error.  Errors: RAID6C_E_ARG,
+ * RAID6C_E_STATE while a replay runs. */
+int raid6c_server_submit(raid6c_server* s, const raid6c_request* reqs, size_t n);
+
+/* Take up to `cap` completions (in completion order); *n receives the count. */
+int raid6c_server_poll(raid6c_server* s, raid6c_completion* out, size_t cap, size_t* n);
+
+/* Block until every submitted request has completed.  Returns RAID6C_E_HIP if
+ * a launch or kernel failed since the server started. */
+int raid6c_server_wait_idle(raid6c_server* s);
+
+/* Open-loop replay: submit request i at (start + arrival_s[i]) seconds, from
+ * the calling thread, whatever the state of earlier requests, then wait for
+ * all; out[i] receives request i's completion, whose arrival_ns is the
+ * scheduled time.  arrival_s must not decrease.  Errors: RAID6C_E_ARG,
+ * RAID6C_E_STATE, RAID6C_E_HIP. */
+int raid6c_server_replay(raid6c_server* s, const raid6c_request* reqs, const double* arrival_s, size_t n,
+                         raid6c_completion* out);
+
+/* Location of a resident stripe: *base receives the device address of its
+ * strip 0 and *strip_stride the bytes between strips (valid until the stripe
+ * is evicted).  Errors: RAID6C_E_ARG (NULL arguments or not resident). */
+int raid6c_server_stripe(raid6c_server* s, uint64_t stripe_id, void** base, uint64_t* strip_stride);
+
+/* Counters of the server so far. */
+int raid6c_server_get_stats(raid6c_server* s, raid6c_server_stats* out);
+
+/* Finish every queued request, stop the threads and free the server. */
+int raid6c_server_destroy(raid6c_server* s);
 
 /* ------------------------------------------------------------------------
  * Launch configuration (used by the autotuner and by tests)

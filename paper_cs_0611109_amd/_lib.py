@@ -36,6 +36,8 @@ SIGNATURES = {
     "raid6c_encode_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
     "raid6c_recover_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _i32p, _i32p, _vp]),
     "raid6c_rs_encode_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
+    "raid6c_write": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, ctypes.POINTER(_vp), _vp]),
+    "raid6c_read_degraded": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _c_int, _c_int, _vp, _vp]),
     "raid6c_vec_mask": (_c_int, [_c_int]),
     "raid6c_unroll_mask": (_c_int, [_c_int, _c_int]),
     "raid6c_tune_set": (_c_int, [_c_int, _c_int, _c_size, _c_int, _c_int, _c_int]),
@@ -52,6 +54,14 @@ SIGNATURES = {
     "raid6c_plan_autotune": (_c_int, [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_float)]),
     "raid6c_plan_destroy": (_c_int, [_vp]),
     "raid6c_run_jobs": (_c_int, [_vp, _c_size, _vp]),
+    "raid6c_server_create": (_c_int, [_vp, _vp]),
+    "raid6c_server_submit": (_c_int, [_vp, _vp, _c_size]),
+    "raid6c_server_poll": (_c_int, [_vp, _vp, _c_size, ctypes.POINTER(_c_size)]),
+    "raid6c_server_wait_idle": (_c_int, [_vp]),
+    "raid6c_server_replay": (_c_int, [_vp, _vp, _vp, _c_size, _vp]),
+    "raid6c_server_get_stats": (_c_int, [_vp, _vp]),
+    "raid6c_server_stripe": (_c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)]),
+    "raid6c_server_destroy": (_c_int, [_vp]),
 }
 
 
@@ -70,6 +80,36 @@ class raid6c_plan_info(ctypes.Structure):
     _fields_ = [("njobs", ctypes.c_uint64), ("nitems", ctypes.c_uint64), ("bytes_moved", ctypes.c_uint64),
                 ("user_bytes", ctypes.c_uint64), ("max_p", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
+
+class raid6c_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_int32), ("k", ctypes.c_int32), ("e0", ctypes.c_int32),
+                ("e1", ctypes.c_int32), ("row_bytes", ctypes.c_uint32), ("stripe_id", ctypes.c_uint64),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class raid6c_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("arrival_ns", ctypes.c_uint64), ("launch_ns", ctypes.c_uint64), ("complete_ns", ctypes.c_uint64)]
+
+
+class raid6c_server_config(ctypes.Structure):
+    _fields_ = [("store_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("plain", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+
+
+class raid6c_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("evictions", ctypes.c_uint64), ("user_bytes", ctypes.c_uint64), ("resident", ctypes.c_uint64),
+                ("store_used", ctypes.c_uint64)]
+
+
+RAID6C_REQ_WRITE = 0
+RAID6C_REQ_READ = 1
+RAID6C_ST_OK = 0
+RAID6C_ST_NOT_RESIDENT = 1
+RAID6C_ST_TOO_LARGE = 2
+RAID6C_ST_INVALID = 3
+RAID6C_ST_DUPLICATE = 4
 
 RAID6C_JOB_ENCODE = 0
 RAID6C_JOB_RECOVER = 1
@@ -173,6 +213,18 @@ def raid6c_recover_2(p, k, row_bytes, strips, e0, e1, stream=None):
                                           _stream(stream)))
 
 
+def raid6c_write(p, k, row_bytes, src, src_strip_stride, strips, stream=None):
+    """Copy a payload of k strips into ``strips[:k]`` and write P, Q (``strips[k:]``)."""
+    return _check(load().raid6c_write(p, k, row_bytes, _ptr(src), src_strip_stride, _ptr_array(list(strips)),
+                                      _stream(stream)))
+
+
+def raid6c_read_degraded(p, k, row_bytes, strips, e0, e1, out, stream=None):
+    """Rebuild erased strips into ``out`` (ascending strip order) without writing the stripe."""
+    return _check(load().raid6c_read_degraded(p, k, row_bytes, _ptr_array(list(strips)), e0, e1, _ptr(out),
+                                              _stream(stream)))
+
+
 def raid6c_encode_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, stream=None):
     return _check(load().raid6c_encode_n(p, k, row_bytes, _ptr(base), strip_stride, stripe_stride,
                                          nstripes, _stream(stream)))
@@ -266,3 +318,54 @@ def raid6c_autotune_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstrip
     _check(load().raid6c_autotune_n(p, k, row_bytes, _ptr(base), strip_stride, stripe_stride, nstripes, op,
                                     _ptr(erasures), reps, _stream(stream), ctypes.byref(ms)))
     return ms.value
+
+
+def raid6c_server_create(store_bytes, max_inflight=4, max_batch=256, plain=False, waves_per_cu=0) -> int:
+    cfg = raid6c_server_config(store_bytes, max_inflight, max_batch, 1 if plain else 0, waves_per_cu)
+    out = _vp()
+    _check(load().raid6c_server_create(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def raid6c_server_submit(server, reqs):
+    arr = reqs if isinstance(reqs, ctypes.Array) else (raid6c_request * len(reqs))(*reqs)
+    return _check(load().raid6c_server_submit(server, ctypes.cast(arr, _vp) if len(arr) else None, len(arr)))
+
+
+def raid6c_server_poll(server, cap=4096):
+    out = (raid6c_completion * cap)()
+    n = _c_size()
+    _check(load().raid6c_server_poll(server, ctypes.cast(out, _vp), cap, ctypes.byref(n)))
+    return list(out[:n.value])
+
+
+def raid6c_server_wait_idle(server):
+    return _check(load().raid6c_server_wait_idle(server))
+
+
+def raid6c_server_replay(server, reqs, arrival_s):
+    """Open-loop replay; returns the completions in request order."""
+    n = len(reqs)
+    arr = reqs if isinstance(reqs, ctypes.Array) else (raid6c_request * n)(*reqs)
+    times = (ctypes.c_double * n)(*arrival_s)
+    out = (raid6c_completion * n)()
+    _check(load().raid6c_server_replay(server, ctypes.cast(arr, _vp), ctypes.cast(times, _vp), n,
+                                       ctypes.cast(out, _vp)))
+    return list(out)
+
+
+def raid6c_server_get_stats(server) -> raid6c_server_stats:
+    st = raid6c_server_stats()
+    _check(load().raid6c_server_get_stats(server, ctypes.byref(st)))
+    return st
+
+
+def raid6c_server_stripe(server, stripe_id):
+    """(device address of strip 0, strip stride) of a resident stripe."""
+    base, stride = _vp(), ctypes.c_uint64()
+    _check(load().raid6c_server_stripe(server, stripe_id, ctypes.byref(base), ctypes.byref(stride)))
+    return base.value, stride.value
+
+
+def raid6c_server_destroy(server):
+    return _check(load().raid6c_server_destroy(server))

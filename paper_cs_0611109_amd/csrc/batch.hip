@@ -30,29 +30,9 @@ int fail(int code, const char* fmt, ...);
 
 namespace {
 
-struct BatchJob {
-  uint8_t* base;          // strip 0
-  uint64_t strip_stride;  // bytes between strips
-  uint32_t row_bytes;
-  int16_t p, k;
-  int16_t op, x, y, pad;  // Case
-};
-
-struct BatchItem {
-  uint32_t job;
-  uint32_t col;  // byte offset of the 256-byte tile within a row
-};
-
-struct BatchArgs {
-  const BatchJob* jobs;
-  const BatchItem* items;
-  uint32_t nitems;
-  uint32_t chunk;  // items taken per counter increment
-  uint32_t* counter;
-};
-
 constexpr int kLanes = 64;
-constexpr int kTileBytes = kLanes * 4;  // one dword per lane and row
+constexpr int kTileBytes = kBatchTileBytes;
+static_assert(kTileBytes == kLanes * 4, "one dword per lane and row");
 
 // Strips whose loads are batched per prime: as many as fit beside the
 // (2p-1) accumulator dwords in the register budget set by the largest prime
@@ -65,7 +45,8 @@ constexpr int batch_unroll(int p) {
 
 template <int P>
 __device__ __forceinline__ void run_item(const BatchJob& j, uint32_t col, uint32_t* lds) {
-  const ColsStrided c{j.base, j.strip_stride, j.row_bytes, col, (uint32_t)((P - 1) * j.row_bytes)};
+  const ColsJob c{j.base, j.strip_stride, j.out0, j.out1, j.src, j.src_stride, j.e0, j.e1,
+                  j.row_bytes, col, (uint32_t)((P - 1) * j.row_bytes)};
   const Case cs{j.op, j.x, j.y};
   tile_recover<P, 1, batch_unroll(P)>(c, j.k, cs, lds, kLanes);
 }
@@ -116,6 +97,21 @@ __global__ void __launch_bounds__(64) batch_kernel(const BatchArgs a) {
     }
   }
 }
+
+}  // namespace
+
+hipError_t batch_launch(const BatchArgs& a, int grid, int max_p, hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, a.counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kLanes), (size_t)max_p * kLanes * 4, stream, a);
+  return hipGetLastError();
+}
+
+const void* batch_kernel_fn() { return (const void*)batch_kernel; }
+const void* batch_reset_fn() { return (const void*)reset_counter; }
+
+namespace {
 
 bool is_odd_prime(int p) {
   if (p < 3 || (p % 2) == 0) return false;
@@ -189,7 +185,7 @@ int build_graph(raid6c_plan* pl) {
   hipGraphNode_t reset_node, batch_node;
   void* reset_params[] = {(void*)&pl->args.counter};
   hipKernelNodeParams rp{};
-  rp.func = (void*)reset_counter;
+  rp.func = (void*)batch_reset_fn();
   rp.gridDim = dim3(1);
   rp.blockDim = dim3(1);
   rp.sharedMemBytes = 0;
@@ -199,7 +195,7 @@ int build_graph(raid6c_plan* pl) {
 
   void* batch_params[] = {(void*)&pl->args};
   hipKernelNodeParams bp{};
-  bp.func = (void*)batch_kernel;
+  bp.func = (void*)batch_kernel_fn();
   bp.gridDim = dim3((unsigned)(pl->cus * pl->sched.waves_per_cu));
   bp.blockDim = dim3(kLanes);
   bp.sharedMemBytes = (unsigned)(pl->max_p * kLanes * 4);
@@ -277,6 +273,9 @@ int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) 
     b.op = (int16_t)cs.op;
     b.x = (int16_t)cs.x;
     b.y = (int16_t)cs.y;
+    b.e0 = -1;
+    b.e1 = -1;
+    b.src = nullptr;
     pl->jobs.push_back(b);
     const uint64_t strip = (uint64_t)(p - 1) * J.row_bytes;
     const int moved = (cs.op == OP_P || cs.op == OP_Q || cs.op == OP_D) ? k + 1 : k + 2;

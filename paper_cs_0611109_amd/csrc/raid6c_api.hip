@@ -222,6 +222,61 @@ int raid6c_recover_2(int p, int k, size_t row_bytes, void* const* strips, int e0
   return recover_single_stripe(p, k, row_bytes, strips, e0, e1, stream);
 }
 
+int raid6c_write(int p, int k, size_t row_bytes, const void* src, size_t src_strip_stride, void* const* strips,
+                 void* stream) {
+  g_last_error.clear();
+  int rc = check_geometry(p, k, row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  const size_t strip = (size_t)(p - 1) * row_bytes;
+  if (src == nullptr || !aligned16(src)) return fail(RAID6C_E_ARG, "src is NULL or not 16-byte aligned");
+  if ((src_strip_stride % 16) != 0 || src_strip_stride < strip)
+    return fail(RAID6C_E_ARG, "src_strip_stride must be a multiple of 16 and >= (p-1)*row_bytes");
+  rc = check_strip_ptrs(k + 2, (const void* const*)strips, strip);
+  if (rc != RAID6C_OK) return rc;
+  const uintptr_t s0 = (uintptr_t)src, s1 = s0 + (uintptr_t)(k - 1) * src_strip_stride + strip;
+  for (int j = 0; j < k + 2; ++j) {
+    const uintptr_t a0 = (uintptr_t)strips[j];
+    if (a0 < s1 && s0 < a0 + strip) return fail(RAID6C_E_ARG, "the payload overlaps strip %d", j);
+  }
+  ZpArgs a;
+  memset(&a, 0, sizeof a);
+  for (int j = 0; j < k + 2; ++j) a.strip[j] = (uint8_t*)strips[j];
+  a.row_bytes = row_bytes;
+  a.k = k;
+  a.e0 = a.e1 = -1;
+  a.src_base = (const uint8_t*)src;
+  a.src_strip_stride = src_strip_stride;
+  return launch_zp(p, KIND_ENCODE, a, 1, stream);
+}
+
+int raid6c_read_degraded(int p, int k, size_t row_bytes, const void* const* strips, int e0, int e1, void* out,
+                         void* stream) {
+  g_last_error.clear();
+  int rc = check_geometry(p, k, row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  if (strips == nullptr) return fail(RAID6C_E_ARG, "strip pointer array is NULL");
+  if (e0 < 0 || e0 > k + 1 || e1 < -1 || e1 > k + 1 || e0 == e1)
+    return fail(RAID6C_E_ARG, "erased strips (%d, %d) must be distinct and in 0..%d", e0, e1, k + 1);
+  if (out == nullptr || !aligned16(out)) return fail(RAID6C_E_ARG, "out is NULL or not 16-byte aligned");
+  const size_t strip = (size_t)(p - 1) * row_bytes;
+  const int lo = (e1 < 0 || e0 < e1) ? e0 : e1;
+  const int hi = (e1 < 0) ? -1 : (e0 < e1 ? e1 : e0);
+  const void* table[kMaxStrips];
+  for (int j = 0; j < k + 2; ++j) table[j] = strips[j];
+  table[lo] = out;
+  if (hi >= 0) table[hi] = (uint8_t*)out + strip;
+  rc = check_strip_ptrs(k + 2, table, strip);
+  if (rc != RAID6C_OK) return rc;
+  ZpArgs a;
+  memset(&a, 0, sizeof a);
+  for (int j = 0; j < k + 2; ++j) a.strip[j] = (uint8_t*)table[j];
+  a.row_bytes = row_bytes;
+  a.k = k;
+  a.e0 = e0;
+  a.e1 = e1;
+  return launch_zp(p, KIND_RECOVER, a, 1, stream);
+}
+
 int raid6c_encode_n(int p, int k, size_t row_bytes, void* base, size_t strip_stride, size_t stripe_stride,
                     size_t nstripes, void* stream) {
   g_last_error.clear();

@@ -62,6 +62,10 @@ struct ZpArgs {
   int32_t e0, e1;              // uniform erasures, used when `erasures` is NULL
   const int32_t* erasures;     // per-stripe pairs (device), or NULL
   int32_t* bad_count;          // device counter of rejected stripes, or NULL
+  const uint8_t* src_base;     // write path: data strip j of stripe s is read from
+                               // src_base + s*src_stripe_stride + j*src_strip_stride
+  uint64_t src_strip_stride;   // and copied to strip j; NULL = encode in place
+  uint64_t src_stripe_stride;
 };
 
 // Launch configuration of a Z_p kernel.
@@ -91,6 +95,45 @@ struct ZpPrimeEntry {
 };
 
 const ZpPrimeEntry* zp_prime_entry(int p);  // NULL when p is not built
+
+// Persistent mixed-geometry kernel (batch.hip), shared by plans and the
+// request server.
+struct BatchJob {
+  uint8_t* base;          // strip 0 of the stripe
+  uint64_t strip_stride;  // bytes between its strips
+  uint8_t* out0;          // where erased strip x0 is written (in place: base + x0*stride)
+  uint8_t* out1;
+  const uint8_t* src;     // write from a payload: data strip j at src + j*src_stride; else NULL
+  uint64_t src_stride;
+  uint32_t row_bytes;
+  int16_t p, k;
+  int16_t op, x, y;       // Case
+  int16_t e0, e1;         // the strips redirected to out0 / out1 (-1: none)
+  int16_t pad;
+};
+
+struct BatchItem {
+  uint32_t job;
+  uint32_t col;  // byte offset of the 256-byte tile within a row
+};
+
+struct BatchArgs {
+  const BatchJob* jobs;
+  const BatchItem* items;
+  uint32_t nitems;
+  uint32_t chunk;  // items taken per counter increment
+  uint32_t* counter;
+};
+
+constexpr int kBatchTileBytes = 256;  // 64 lanes x one dword
+
+// Enqueue counter reset + persistent kernel on `stream` (grid work-groups of
+// one wave, LDS for primes up to max_p).
+hipError_t batch_launch(const BatchArgs& a, int grid, int max_p, hipStream_t stream);
+
+// Kernel functions, for graph nodes.
+const void* batch_kernel_fn();
+const void* batch_reset_fn();
 
 // Reed-Solomon GF(256) comparison kernel (rs_kernels.hip).
 struct RsArgs {

@@ -1,0 +1,580 @@
+// serve.hip -- a request server with continuous batching.
+//
+// Clients submit writes (a payload becomes a new resident stripe: data strips
+// copied into the store and P, Q computed in the same pass) and degraded
+// reads (one or two strips of a resident stripe rebuilt into a client
+// buffer).  The stripe store is one device allocation (the HBM budget) used
+// as a ring: stripes are placed in arrival order and the oldest idle stripes
+// are evicted when a write needs room.
+//
+// A scheduler thread admits pending requests into free "slots" (a stream, an
+// event and job/item tables) and launches each slot's requests as one
+// persistent kernel (the plan kernel of batch.hip); requests that arrive
+// while slots are busy are admitted into the next free slot, so up to
+// max_inflight batches overlap on the device.  A completion thread polls the
+// slots' events, stamps completion times and releases stripes.  With
+// `plain` set, every request is instead one plain launch (raid6c_write /
+// raid6c_read_degraded) on a single stream: the per-request path.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/raid6c.h"
+#include "raid6c_internal.h"
+
+namespace raid6c {
+int fail(int code, const char* fmt, ...);
+}
+
+using namespace raid6c;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+bool is_odd_prime(int p) {
+  if (p < 3 || (p % 2) == 0) return false;
+  for (int d = 3; d * d <= p; d += 2)
+    if (p % d == 0) return false;
+  return true;
+}
+
+uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+struct Resident {
+  uint64_t id;
+  uint64_t off;    // byte offset in the store
+  uint64_t bytes;  // reserved bytes
+  int p, k;
+  uint32_t row_bytes;
+  int refs;        // admitted requests not yet complete
+  bool ready;      // its write has completed
+  bool evicted;
+};
+
+struct Pending {
+  raid6c_request req;
+  uint64_t arrival_ns;
+  size_t index;    // position in a replay, else SIZE_MAX
+};
+
+struct InFlight {
+  raid6c_request req;
+  uint64_t arrival_ns;
+  size_t index;
+  Resident* stripe;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  BatchJob* h_jobs = nullptr;   // pinned
+  BatchItem* h_items = nullptr; // pinned
+  void* d_mem = nullptr;        // jobs | items | counter
+  size_t cap_jobs = 0, cap_items = 0;
+  std::vector<InFlight> reqs;
+  uint64_t launch_ns = 0;
+  bool busy = false;      // owns requests
+  bool launched = false;  // its completion event has been recorded
+};
+
+}  // namespace
+
+struct raid6c_server {
+  raid6c_server_config cfg{};
+  int device = 0;
+  int cus = 256;
+  uint8_t* store = nullptr;
+  uint64_t head = 0;             // next free byte (ring)
+  std::deque<Resident*> fifo;    // resident stripes, oldest first
+  std::unordered_map<uint64_t, Resident*> index;
+  std::vector<Slot> slots;
+  hipStream_t plain_stream = nullptr;
+
+  std::mutex mu;
+  std::condition_variable cv_sched;  // pending work or a free slot
+  std::condition_variable cv_done;   // completions
+  std::deque<Pending> pending;
+  std::deque<raid6c_completion> done;
+  raid6c_completion* replay_out = nullptr;
+  size_t outstanding = 0;            // submitted, not complete
+  bool stopping = false;
+  raid6c_server_stats stats{};
+  Clock::time_point t0 = Clock::now();
+  std::thread scheduler, completer;
+  int thread_error = 0;
+
+  uint64_t now_ns() const {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+uint64_t stripe_bytes(int p, int k, uint32_t w) { return round_up((uint64_t)(k + 2) * (p - 1) * w, 256); }
+
+int check_request(const raid6c_request& r) {
+  if (r.kind != RAID6C_REQ_WRITE && r.kind != RAID6C_REQ_READ) return RAID6C_ST_INVALID;
+  if (r.kind == RAID6C_REQ_READ) return RAID6C_ST_OK;  // geometry comes from the stripe
+  if (!is_odd_prime(r.p) || r.p > kMaxPrime || r.k < 1 || r.k > r.p) return RAID6C_ST_INVALID;
+  if (r.row_bytes == 0 || (r.row_bytes % 16) != 0) return RAID6C_ST_INVALID;
+  if ((uint64_t)(r.p - 1) * r.row_bytes >= (1ull << 31)) return RAID6C_ST_INVALID;
+  if (r.src == nullptr || ((uintptr_t)r.src & 15u) != 0) return RAID6C_ST_INVALID;
+  return RAID6C_ST_OK;
+}
+
+// Place a new stripe in the ring, evicting the oldest idle stripes as needed.
+// Returns the stripe, or nullptr when it must wait (the oldest stripe is busy)
+// or can never fit (*never = true).
+Resident* place(raid6c_server* s, const raid6c_request& r, bool* never) {
+  const uint64_t need = stripe_bytes(r.p, r.k, r.row_bytes);
+  *never = need > s->cfg.store_bytes;
+  if (*never) return nullptr;
+  for (;;) {
+    uint64_t off = s->head;
+    if (off + need > s->cfg.store_bytes) off = 0;  // wrap
+    // The span [off, off+need) must be free of resident stripes.
+    bool blocked = false;
+    bool overlap = false;
+    for (Resident* o : s->fifo) {
+      if (o->off < off + need && off < o->off + o->bytes) {
+        overlap = true;
+        break;
+      }
+    }
+    if (!overlap) {
+      Resident* st = new Resident{r.stripe_id, off, need, r.p, r.k, r.row_bytes, 0, false, false};
+      s->fifo.push_back(st);
+      s->index[r.stripe_id] = st;
+      s->head = off + need;
+      return st;
+    }
+    // Evict the oldest stripe if it is idle, else wait.
+    Resident* oldest = s->fifo.front();
+    if (oldest->refs > 0) blocked = true;
+    if (blocked) return nullptr;
+    s->fifo.pop_front();
+    s->index.erase(oldest->id);
+    delete oldest;
+    s->stats.evictions++;
+  }
+}
+
+void complete_one(raid6c_server* s, const raid6c_request& req, uint64_t arrival, size_t index, int status,
+                  uint64_t launch_ns, uint64_t done_ns, int batch, uint64_t user_bytes = 0) {
+  raid6c_completion c{};
+  c.tag = req.tag;
+  c.status = status;
+  c.batch_size = batch;
+  c.arrival_ns = arrival;
+  c.launch_ns = launch_ns;
+  c.complete_ns = done_ns;
+  if (s->replay_out != nullptr && index != SIZE_MAX) s->replay_out[index] = c;
+  else s->done.push_back(c);
+  s->stats.completed++;
+  if (status == RAID6C_ST_OK) s->stats.user_bytes += user_bytes;
+  s->outstanding--;
+}
+
+bool grow_slot(Slot& sl, size_t jobs, size_t items) {
+  if (jobs <= sl.cap_jobs && items <= sl.cap_items) return true;
+  const size_t nj = std::max(jobs, sl.cap_jobs * 2 + 16), ni = std::max(items, sl.cap_items * 2 + 256);
+  if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
+  if (sl.h_items) (void)hipHostFree(sl.h_items);
+  if (sl.d_mem) (void)hipFree(sl.d_mem);
+  sl.h_jobs = nullptr;
+  sl.h_items = nullptr;
+  sl.d_mem = nullptr;
+  sl.cap_jobs = sl.cap_items = 0;
+  if (hipHostMalloc((void**)&sl.h_jobs, nj * sizeof(BatchJob), 0) != hipSuccess) return false;
+  if (hipHostMalloc((void**)&sl.h_items, ni * sizeof(BatchItem), 0) != hipSuccess) return false;
+  if (hipMalloc(&sl.d_mem, nj * sizeof(BatchJob) + ni * sizeof(BatchItem) + 256) != hipSuccess) return false;
+  sl.cap_jobs = nj;
+  sl.cap_items = ni;
+  return true;
+}
+
+// Launch one slot's requests.  Called without the lock.
+hipError_t launch_slot(raid6c_server* s, Slot& sl) {
+  if (s->cfg.plain) {
+    // One plain launch per request, on one stream.
+    for (const InFlight& f : sl.reqs) {
+      const Resident* st = f.stripe;
+      const size_t strip = (size_t)(st->p - 1) * st->row_bytes;
+      void* strips[kMaxStrips];
+      for (int j = 0; j < st->k + 2; ++j) strips[j] = s->store + st->off + (size_t)j * strip;
+      int rc;
+      if (f.req.kind == RAID6C_REQ_WRITE)
+        rc = raid6c_write(st->p, st->k, st->row_bytes, f.req.src, strip, strips, sl.stream);
+      else
+        rc = raid6c_read_degraded(st->p, st->k, st->row_bytes, (const void* const*)strips, f.req.e0, f.req.e1,
+                                  f.req.dst, sl.stream);
+      if (rc != RAID6C_OK) return hipErrorLaunchFailure;
+    }
+    return hipEventRecord(sl.done, sl.stream);
+  }
+  size_t nitems = 0;
+  for (size_t i = 0; i < sl.reqs.size(); ++i) {
+    const InFlight& f = sl.reqs[i];
+    const Resident* st = f.stripe;
+    const size_t strip = (size_t)(st->p - 1) * st->row_bytes;
+    BatchJob& j = sl.h_jobs[i];
+    memset(&j, 0, sizeof j);
+    j.base = s->store + st->off;
+    j.strip_stride = strip;
+    j.row_bytes = st->row_bytes;
+    j.p = (int16_t)st->p;
+    j.k = (int16_t)st->k;
+    j.e0 = j.e1 = -1;
+    if (f.req.kind == RAID6C_REQ_WRITE) {
+      j.op = OP_PQ;
+      j.x = j.y = -1;
+      j.src = (const uint8_t*)f.req.src;
+      j.src_stride = strip;
+    } else {
+      const Case cs = classify(st->k, f.req.e0, f.req.e1);
+      j.op = (int16_t)cs.op;
+      j.x = (int16_t)cs.x;
+      j.y = (int16_t)cs.y;
+      const int lo = (f.req.e1 < 0 || f.req.e0 < f.req.e1) ? f.req.e0 : f.req.e1;
+      const int hi = f.req.e1 < 0 ? -1 : (f.req.e0 < f.req.e1 ? f.req.e1 : f.req.e0);
+      j.e0 = (int16_t)lo;
+      j.out0 = (uint8_t*)f.req.dst;
+      j.e1 = (int16_t)hi;
+      j.out1 = (uint8_t*)f.req.dst + strip;
+    }
+    for (uint32_t c = 0; c < st->row_bytes; c += kBatchTileBytes) sl.h_items[nitems++] = BatchItem{(uint32_t)i, c};
+  }
+  BatchJob* d_jobs = (BatchJob*)sl.d_mem;
+  BatchItem* d_items = (BatchItem*)((uint8_t*)sl.d_mem + sl.cap_jobs * sizeof(BatchJob));
+  uint32_t* d_counter = (uint32_t*)((uint8_t*)d_items + sl.cap_items * sizeof(BatchItem));
+  hipError_t e = hipMemcpyAsync(d_jobs, sl.h_jobs, sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, sl.stream);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(d_items, sl.h_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, sl.stream);
+  if (e != hipSuccess) return e;
+  int max_p = 3;
+  for (const InFlight& f : sl.reqs) max_p = std::max(max_p, f.stripe->p);
+  BatchArgs a{d_jobs, d_items, (uint32_t)nitems, 4u, d_counter};
+  const int waves = s->cfg.waves_per_cu > 0 ? s->cfg.waves_per_cu : 8;
+  int grid = s->cus * waves;
+  const int need = (int)((nitems + a.chunk - 1) / a.chunk);
+  if (need < grid) grid = std::max(1, need);
+  e = batch_launch(a, grid, max_p, sl.stream);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(sl.done, sl.stream);
+}
+
+void scheduler_loop(raid6c_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    Slot* free_slot = nullptr;
+    for (Slot& sl : s->slots)
+      if (!sl.busy) {
+        free_slot = &sl;
+        break;
+      }
+    if (s->stopping && s->pending.empty()) return;
+    if (free_slot == nullptr || s->pending.empty()) {
+      s->cv_sched.wait(lk);
+      continue;
+    }
+    // Admit requests in arrival order (a read of a stripe whose write is still
+    // in flight, or a write that must wait for room, is skipped this round;
+    // later requests may pass it).
+    Slot& sl = *free_slot;
+    sl.reqs.clear();
+    const size_t max_batch = s->cfg.plain ? 1 : (size_t)std::max(1, s->cfg.max_batch);
+    size_t items = 0;
+    std::vector<uint64_t> waiting_writes;  // skipped writes: reads of them wait too
+    for (auto it = s->pending.begin(); it != s->pending.end() && sl.reqs.size() < max_batch;) {
+      const raid6c_request& r = it->req;
+      int status = check_request(r);
+      Resident* st = nullptr;
+      bool wait = false;
+      if (status == RAID6C_ST_OK && r.kind == RAID6C_REQ_READ &&
+          std::find(waiting_writes.begin(), waiting_writes.end(), r.stripe_id) != waiting_writes.end()) {
+        ++it;
+        continue;
+      }
+      if (status == RAID6C_ST_OK && r.kind == RAID6C_REQ_WRITE) {
+        if (s->index.count(r.stripe_id)) {
+          status = RAID6C_ST_DUPLICATE;
+        } else {
+          bool never = false;
+          st = place(s, r, &never);
+          if (never) status = RAID6C_ST_TOO_LARGE;
+          else if (st == nullptr) wait = true;
+        }
+      } else if (status == RAID6C_ST_OK) {
+        auto f = s->index.find(r.stripe_id);
+        if (f == s->index.end()) {
+          status = RAID6C_ST_NOT_RESIDENT;
+        } else {
+          st = f->second;
+          if (!st->ready) {
+            wait = true;
+          } else if (classify(st->k, r.e0, r.e1).op == OP_BAD || r.dst == nullptr ||
+                     ((uintptr_t)r.dst & 15u) != 0) {
+            status = RAID6C_ST_INVALID;
+            st = nullptr;
+          }
+        }
+      }
+      if (wait) {
+        if (r.kind == RAID6C_REQ_WRITE) waiting_writes.push_back(r.stripe_id);
+        ++it;
+        continue;
+      }
+      if (status != RAID6C_ST_OK) {
+        const uint64_t t = s->now_ns();
+        complete_one(s, r, it->arrival_ns, it->index, status, t, t, 0);
+        it = s->pending.erase(it);
+        s->cv_done.notify_all();
+        continue;
+      }
+      st->refs++;
+      sl.reqs.push_back(InFlight{r, it->arrival_ns, it->index, st});
+      items += (st->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
+      it = s->pending.erase(it);
+    }
+    if (sl.reqs.empty()) {
+      // Everything pending waits on in-flight work.
+      s->cv_sched.wait(lk);
+      continue;
+    }
+    sl.busy = true;
+    s->stats.batches++;
+    lk.unlock();
+    hipError_t e = hipSuccess;
+    if (!s->cfg.plain && !grow_slot(sl, sl.reqs.size(), items)) e = hipErrorOutOfMemory;
+    sl.launch_ns = s->now_ns();
+    if (e == hipSuccess) e = launch_slot(s, sl);
+    lk.lock();
+    if (e == hipSuccess) sl.launched = true;
+    if (e != hipSuccess) {
+      s->thread_error = RAID6C_E_HIP;
+      // Fail the batch's requests so callers are not left waiting.
+      const uint64_t t = s->now_ns();
+      for (const InFlight& f : sl.reqs) {
+        f.stripe->refs--;
+        complete_one(s, f.req, f.arrival_ns, f.index, RAID6C_ST_INVALID, t, t, 0);
+      }
+      sl.reqs.clear();
+      sl.busy = false;
+      s->cv_done.notify_all();
+    }
+  }
+}
+
+void completer_loop(raid6c_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    bool any_busy = false;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->stopping && s->outstanding == 0 && s->pending.empty()) {
+        bool idle = true;
+        for (Slot& sl : s->slots) idle &= !sl.busy;
+        if (idle) return;
+      }
+    }
+    for (Slot& sl : s->slots) {
+      bool busy;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        busy = sl.busy && sl.launched;
+      }
+      if (!busy) continue;
+      any_busy = true;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipErrorNotReady) continue;
+      const uint64_t t = s->now_ns();
+      std::lock_guard<std::mutex> lk(s->mu);
+      const int n = (int)sl.reqs.size();
+      for (const InFlight& f : sl.reqs) {
+        if (f.req.kind == RAID6C_REQ_WRITE) f.stripe->ready = true;
+        f.stripe->refs--;
+        const uint64_t user = (uint64_t)f.stripe->k * (f.stripe->p - 1) * f.stripe->row_bytes;
+        complete_one(s, f.req, f.arrival_ns, f.index, q == hipSuccess ? RAID6C_ST_OK : RAID6C_ST_INVALID,
+                     sl.launch_ns, t, n, user);
+      }
+      if (q != hipSuccess) s->thread_error = RAID6C_E_HIP;
+      sl.reqs.clear();
+      sl.launch_ns = 0;
+      sl.launched = false;
+      sl.busy = false;
+      s->cv_sched.notify_all();
+      s->cv_done.notify_all();
+    }
+    if (!any_busy) {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_done.wait_for(lk, std::chrono::microseconds(200));
+    } else {
+      std::this_thread::yield();
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int raid6c_server_create(const raid6c_server_config* cfg, raid6c_server** out) {
+  if (cfg == nullptr || out == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
+  *out = nullptr;
+  if (cfg->store_bytes < 4096 || cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_batch < 1 ||
+      cfg->max_batch > 65536 || cfg->waves_per_cu < 0 || cfg->waves_per_cu > 32)
+    return fail(RAID6C_E_ARG, "invalid server configuration");
+  raid6c_server* s = new (std::nothrow) raid6c_server();
+  if (s == nullptr) return fail(RAID6C_E_NOMEM, "out of host memory");
+  s->cfg = *cfg;
+  (void)hipGetDevice(&s->device);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) == hipSuccess && cus > 0)
+    s->cus = cus;
+  if (hipMalloc((void**)&s->store, cfg->store_bytes) != hipSuccess) {
+    delete s;
+    return fail(RAID6C_E_NOMEM, "cannot allocate a %llu-byte stripe store", (unsigned long long)cfg->store_bytes);
+  }
+  s->slots.resize((size_t)cfg->max_inflight);
+  hipError_t e = hipSuccess;
+  if (cfg->plain) e = hipStreamCreateWithFlags(&s->plain_stream, hipStreamNonBlocking);
+  for (Slot& sl : s->slots) {
+    if (e != hipSuccess) break;
+    if (cfg->plain) sl.stream = s->plain_stream;
+    else e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    raid6c_server_destroy(s);
+    return fail(RAID6C_E_HIP, "stream or event creation failed: %s", hipGetErrorString(e));
+  }
+  s->scheduler = std::thread(scheduler_loop, s);
+  s->completer = std::thread(completer_loop, s);
+  *out = s;
+  return RAID6C_OK;
+}
+
+int raid6c_server_submit(raid6c_server* s, const raid6c_request* reqs, size_t n) {
+  if (s == nullptr || (reqs == nullptr && n != 0)) return fail(RAID6C_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->replay_out != nullptr) return fail(RAID6C_E_STATE, "a replay is running");
+  const uint64_t t = s->now_ns();
+  for (size_t i = 0; i < n; ++i) s->pending.push_back(Pending{reqs[i], t, SIZE_MAX});
+  s->outstanding += n;
+  s->stats.submitted += n;
+  s->cv_sched.notify_all();
+  return RAID6C_OK;
+}
+
+int raid6c_server_poll(raid6c_server* s, raid6c_completion* out, size_t cap, size_t* n) {
+  if (s == nullptr || n == nullptr || (out == nullptr && cap != 0)) return fail(RAID6C_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  size_t m = 0;
+  while (m < cap && !s->done.empty()) {
+    out[m++] = s->done.front();
+    s->done.pop_front();
+  }
+  *n = m;
+  return RAID6C_OK;
+}
+
+int raid6c_server_wait_idle(raid6c_server* s) {
+  if (s == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
+  return s->thread_error;
+}
+
+int raid6c_server_replay(raid6c_server* s, const raid6c_request* reqs, const double* arrival_s, size_t n,
+                         raid6c_completion* out) {
+  if (s == nullptr || ((reqs == nullptr || arrival_s == nullptr || out == nullptr) && n != 0))
+    return fail(RAID6C_E_ARG, "NULL argument");
+  for (size_t i = 1; i < n; ++i)
+    if (arrival_s[i] < arrival_s[i - 1]) return fail(RAID6C_E_ARG, "arrival times must not decrease");
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
+    if (s->replay_out != nullptr) return fail(RAID6C_E_STATE, "a replay is running");
+    s->replay_out = out;
+  }
+  // Open loop: request i is submitted at start + arrival_s[i], whatever the
+  // state of earlier requests; its latency counts from that scheduled time.
+  const uint64_t start = s->now_ns() + 1000000;  // 1 ms to get going
+  for (size_t i = 0; i < n; ++i) {
+    const uint64_t due = start + (uint64_t)(arrival_s[i] * 1e9);
+    while (s->now_ns() < due) {
+      const uint64_t left = due - s->now_ns();
+      if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->pending.push_back(Pending{reqs[i], due, i});
+    s->outstanding++;
+    s->stats.submitted++;
+    s->cv_sched.notify_all();
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
+  s->replay_out = nullptr;
+  return s->thread_error;
+}
+
+int raid6c_server_stripe(raid6c_server* s, uint64_t stripe_id, void** base, uint64_t* strip_stride) {
+  if (s == nullptr || base == nullptr || strip_stride == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto f = s->index.find(stripe_id);
+  if (f == s->index.end()) return fail(RAID6C_E_ARG, "stripe %llu is not resident", (unsigned long long)stripe_id);
+  *base = s->store + f->second->off;
+  *strip_stride = (uint64_t)(f->second->p - 1) * f->second->row_bytes;
+  return RAID6C_OK;
+}
+
+int raid6c_server_get_stats(raid6c_server* s, raid6c_server_stats* out) {
+  if (s == nullptr || out == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->resident = s->fifo.size();
+  uint64_t used = 0;
+  for (const Resident* r : s->fifo) used += r->bytes;
+  out->store_used = used;
+  return RAID6C_OK;
+}
+
+int raid6c_server_destroy(raid6c_server* s) {
+  if (s == nullptr) return RAID6C_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+    s->cv_sched.notify_all();
+    s->cv_done.notify_all();
+  }
+  if (s->scheduler.joinable()) s->scheduler.join();
+  if (s->completer.joinable()) s->completer.join();
+  for (Slot& sl : s->slots) {
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream && sl.stream != s->plain_stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
+    if (sl.h_items) (void)hipHostFree(sl.h_items);
+    if (sl.d_mem) (void)hipFree(sl.d_mem);
+  }
+  if (s->plain_stream) (void)hipStreamDestroy(s->plain_stream);
+  for (Resident* r : s->fifo) delete r;
+  if (s->store) (void)hipFree(s->store);
+  delete s;
+  return RAID6C_OK;
+}
+
+}  // extern "C"

@@ -107,33 +107,55 @@ template <> struct bufio<4> {
   }
 };
 
-// Where one stripe's strips are, for one thread's column slice.  Two forms,
-// both offering strip(j) (a buffer resource over strip j), W() (row bytes)
-// and col (this thread's byte offset within a row):
+// Where one stripe's strips are, for one thread's column slice.  Both forms
+// offer strip(j) (a buffer resource over strip j, the place the stripe's
+// strip lives and results are written), src(j) (where data strip j is read
+// from: strip(j), or a separate source when the stripe is being written from
+// a payload), copy() (true when src differs from strip, so data rows read from
+// src are also stored to strip), W() (row bytes) and col (this thread's byte
+// offset within a row).
 //  * ColsTable: a table of k+2 strip addresses (kernel argument) plus a
-//    per-stripe offset;
-//  * ColsStrided: strip j at base + j * strip_stride (batched jobs).
+//    per-stripe offset; an optional source table for writes.
+//  * ColsJob: strip j at base + j * strip_stride except that the erased
+//    strips e0, e1 may be redirected to out0, out1 (a degraded read rebuilds
+//    them into a separate buffer); an optional contiguous source for writes.
 struct ColsTable {
   const ZpArgs* a;
   uint64_t stripe_off;   // stripe * stripe_stride
+  uint64_t src_off;      // stripe * src_stripe_stride
   uint32_t col;
   uint32_t strip_bytes;  // (p-1) * row_bytes
 
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t strip(int j) const {
     return make_rsrc(a->strip[j] + stripe_off, strip_bytes);
   }
+  __device__ __forceinline__ bool copy() const { return a->src_base != nullptr; }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t src(int j) const {
+    return copy() ? make_rsrc(a->src_base + src_off + (uint64_t)j * a->src_strip_stride, strip_bytes) : strip(j);
+  }
   __device__ __forceinline__ uint64_t W() const { return a->row_bytes; }
 };
 
-struct ColsStrided {
+struct ColsJob {
   uint8_t* base;
   uint64_t strip_stride;
+  uint8_t* out0;         // where strip e0 is written (base + e0 * strip_stride in place)
+  uint8_t* out1;
+  const uint8_t* src_base;  // data source of a write, or NULL
+  uint64_t src_stride;
+  int e0, e1;
   uint32_t row_bytes;
   uint32_t col;
   uint32_t strip_bytes;
 
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t strip(int j) const {
-    return make_rsrc(base + (uint64_t)j * strip_stride, strip_bytes);
+    uint8_t* p = j == e0 ? out0 : j == e1 ? out1 : base + (uint64_t)j * strip_stride;
+    return make_rsrc(p, strip_bytes);
+  }
+  __device__ __forceinline__ bool copy() const { return src_base != nullptr; }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t src(int j) const {
+    return copy() ? make_rsrc(src_base + (uint64_t)j * src_stride, strip_bytes)
+                  : make_rsrc(base + (uint64_t)j * strip_stride, strip_bytes);
   }
   __device__ __forceinline__ uint64_t W() const { return row_bytes; }
 };
@@ -179,12 +201,23 @@ __device__ __forceinline__ void stream_data(const C& c, int k, int x, int y,
 #pragma unroll
         for (int r = 0; r < R; ++r) v[u][r] = (VT)(0u);
       } else {
-        const __amdgpu_buffer_rsrc_t b = c.strip(tt);
+        const __amdgpu_buffer_rsrc_t b = c.src(tt);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[u][r] = ld<VT>(b, r, W, c.col);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
+    if (c.copy()) {
+      // Writing a stripe from a payload: the data rows go to the stripe too.
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int tt = t - u;
+        if (tt == x || tt == y) continue;
+        const __amdgpu_buffer_rsrc_t d = c.strip(tt);
+#pragma unroll
+        for (int r = 0; r < R; ++r) st<VT>(d, r, W, c.col, v[u][r]);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (HQ) rotate_up<P>(aq);
@@ -199,11 +232,16 @@ __device__ __forceinline__ void stream_data(const C& c, int k, int x, int y,
     if (HQ) rotate_up<P>(aq);
     __builtin_amdgcn_sched_barrier(0);
     if (t == x || t == y) continue;
-    const __amdgpu_buffer_rsrc_t b = c.strip(t);
+    const __amdgpu_buffer_rsrc_t b = c.src(t);
     VT v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = ld<VT>(b, r, W, c.col);
     __builtin_amdgcn_sched_barrier(0);
+    if (c.copy()) {
+      const __amdgpu_buffer_rsrc_t d = c.strip(t);
+#pragma unroll
+      for (int r = 0; r < R; ++r) st<VT>(d, r, W, c.col, v[r]);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (HP) ap[r] ^= v[r];

@@ -33,7 +33,8 @@ __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
   const uint32_t tile = blockIdx.x - stripe * a.tiles;
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
-  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
+  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
+                    (uint32_t)((P - 1) * a.row_bytes)};
   tile_encode<P, V, U>(c, a.k, true, true);
 }
 
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   }
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
-  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, col, (uint32_t)((P - 1) * a.row_bytes)};
+  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, 0, col, (uint32_t)((P - 1) * a.row_bytes)};
   uint32_t* lds = reinterpret_cast<uint32_t*>(smem) + threadIdx.x;
   tile_recover<P, V, U>(c, a.k, cs, lds, (int)blockDim.x);
 }
