@@ -12,7 +12,9 @@ uniformly from its 91 pairs (two data strips, data + P, data + Q, or P + Q).
 Also reported: per-kernel HIP-event timing and latency percentiles, the
 roofline of the dominant kernel (HBM bound), the GF(256) Reed-Solomon P+Q
 kernel on the same bytes, recovery throughput at p = 29, k = 28, 1 KiB rows,
-8192 stripes, and the CPU oracle timed on a bounded sample of the workload.
+8192 stripes, 20,000 mixed stripes in one plan run against 20,000 plain
+launches, a served Poisson request stream against per-request plain launches,
+and the CPU oracle timed on a bounded sample of the workload.
 """
 
 from __future__ import annotations
@@ -187,7 +189,71 @@ def extras(reps, stream):
     del b
     torch.cuda.empty_cache()
     out["batched_20000_mixed"] = batched_mixed(reps, stream)
+    out["served_poisson"] = served_poisson()
     return out
+
+
+def served_poisson(n=4000, seed=5):
+    """Open-loop Poisson stream of writes (60%) and degraded reads (40%, one or
+    two erased strips) on p in {11,13,29,37}, k = p-1, payloads log-uniform over
+    4 KiB..4 MiB, pre-staged in device memory, 32 GiB stripe store.  First the
+    saturation rate R of the per-request plain path (all requests at t=0), then
+    both paths at 0.8 R: p50/p99 latency (completion - scheduled arrival) and
+    user GB/s."""
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    reqs = datagen.serve_requests(seed, n, qps=1.0)
+    pay_off, out_off, pp, po = {}, {}, 0, 0
+    for q in reqs:
+        strip = (q.p - 1) * q.row_bytes
+        if q.kind == "write":
+            pay_off[q.index] = pp
+            pp += q.k * strip
+        else:
+            out_off[q.index] = po
+            po += 2 * strip
+    pay = torch.empty(pp, dtype=torch.uint8, device="cuda:0")
+    pay.random_(0, 256)
+    outb = torch.empty(max(po, 16), dtype=torch.uint8, device="cuda:0")
+    creq = []
+    for q in reqs:
+        if q.kind == "write":
+            creq.append(r.raid6c_request(r.RAID6C_REQ_WRITE, q.p, q.k, -1, -1, q.row_bytes, q.index,
+                                         pay.data_ptr() + pay_off[q.index], None, q.index))
+        else:
+            creq.append(r.raid6c_request(r.RAID6C_REQ_READ, 0, 0, q.e0, q.e1, 0, q.target, None,
+                                         outb.data_ptr() + out_off[q.index], q.index))
+    arr = (r.raid6c_request * n)(*creq)
+    base_t = [q.arrival_s for q in reqs]
+    torch.cuda.synchronize()
+
+    def run(plain, times):
+        srv = r.raid6c_server_create(32 << 30, max_inflight=32 if plain else 8, max_batch=64, plain=plain)
+        try:
+            comps = r.raid6c_server_replay(srv, arr, times)
+            st = r.raid6c_server_get_stats(srv)
+        finally:
+            r.raid6c_server_destroy(srv)
+        bad = sum(c.status != r.RAID6C_ST_OK for c in comps)
+        lat = [(c.complete_ns - c.arrival_ns) / 1e6 for c in comps]
+        span = (max(c.complete_ns for c in comps) - min(c.arrival_ns for c in comps)) / 1e9
+        return {"p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
+                "GBps_user": round(st.user_bytes / span / 1e9, 1), "requests_per_s": round(n / span, 1),
+                "batches": st.batches, "failed": bad}
+
+    zero = [0.0] * n
+    sat_plain = run(True, zero)
+    sat_served = run(False, zero)
+    rate = 0.8 * sat_plain["requests_per_s"]
+    times = [t / rate for t in base_t]
+    high = 4.0 * sat_plain["requests_per_s"]
+    return {"requests": n, "writes": sum(q.kind == "write" for q in reqs),
+            "saturation_plain": sat_plain, "saturation_served": sat_served,
+            "qps": round(rate, 1), "served_at_qps": run(False, times), "plain_at_qps": run(True, times),
+            "qps_4x_plain_saturation": round(high, 1),
+            "served_at_4x": run(False, [t / high for t in base_t])}
 
 
 def batched_mixed(reps, stream):

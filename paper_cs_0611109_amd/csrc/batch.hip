@@ -9,7 +9,9 @@
 // ordered largest-first so the tail of the launch is made of small items.
 //
 // The graph holds two nodes: a one-thread kernel that zeroes the counter
-// (a kernel, not a memset node) and the persistent kernel.
+// (a kernel, not a memset node) and the persistent kernel.  (The request
+// server launches the kernel directly and instead advances the counter's base
+// by the exact number of increments each run takes.)
 #include <hip/hip_runtime.h>
 
 #include <stdlib.h>
@@ -51,7 +53,7 @@ __device__ __forceinline__ void run_item(const BatchJob& j, uint32_t col, uint32
   tile_recover<P, 1, batch_unroll(P)>(c, j.k, cs, lds, kLanes);
 }
 
-__global__ void reset_counter(uint32_t* counter) { *counter = 0u; }
+__global__ void reset_counter(uint64_t* counter) { *counter = 0ull; }
 
 __global__ void __launch_bounds__(64) batch_kernel(const BatchArgs a) {
   extern __shared__ __align__(16) uint32_t smem[];
@@ -59,7 +61,10 @@ __global__ void __launch_bounds__(64) batch_kernel(const BatchArgs a) {
   uint32_t* lds = smem + lane;
   for (;;) {
     uint32_t got = 0;
-    if (lane == 0) got = atomicAdd(a.counter, a.chunk);
+    if (lane == 0) {
+      const uint64_t v = atomicAdd((unsigned long long*)a.counter, (unsigned long long)a.chunk) - a.base;
+      got = v < a.nitems ? (uint32_t)v : a.nitems;
+    }
     const uint32_t first = __builtin_amdgcn_readfirstlane(got);
     if (first >= a.nitems) break;
     const uint32_t last = min(first + a.chunk, a.nitems);
@@ -101,9 +106,6 @@ __global__ void __launch_bounds__(64) batch_kernel(const BatchArgs a) {
 }  // namespace
 
 hipError_t batch_launch(const BatchArgs& a, int grid, int max_p, hipStream_t stream) {
-  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, a.counter);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kLanes), (size_t)max_p * kLanes * 4, stream, a);
   return hipGetLastError();
 }
@@ -324,7 +326,8 @@ int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) 
   }
   pl->args.jobs = (const BatchJob*)pl->dmem;
   pl->args.items = (const BatchItem*)((uint8_t*)pl->dmem + jb);
-  pl->args.counter = (uint32_t*)((uint8_t*)pl->dmem + jb + ib);
+  pl->args.counter = (uint64_t*)((uint8_t*)pl->dmem + jb + ib);
+  pl->args.base = 0;
   pl->args.nitems = (uint32_t)pl->items.size();
   if (!pl->jobs.empty() &&
       (e = hipMemcpy((void*)pl->args.jobs, pl->jobs.data(), pl->jobs.size() * sizeof(BatchJob),

@@ -121,14 +121,22 @@ struct BatchArgs {
   const BatchJob* jobs;
   const BatchItem* items;
   uint32_t nitems;
-  uint32_t chunk;  // items taken per counter increment
-  uint32_t* counter;
+  uint32_t chunk;       // items taken per counter increment
+  uint64_t* counter;    // work counter: the run takes values base, base+chunk, ...
+  uint64_t base;
 };
+
+// Value of the counter after a run of `nitems` items with `grid` work-groups
+// started at `base`: every work-group stops at its first pop past the end,
+// so the run takes exactly ceil(nitems/chunk) + grid increments of `chunk`.
+inline uint64_t batch_counter_after(uint64_t base, uint32_t nitems, uint32_t chunk, uint32_t grid) {
+  return base + ((uint64_t)(nitems + chunk - 1) / chunk + grid) * chunk;
+}
 
 constexpr int kBatchTileBytes = 256;  // 64 lanes x one dword
 
-// Enqueue counter reset + persistent kernel on `stream` (grid work-groups of
-// one wave, LDS for primes up to max_p).
+// Enqueue the persistent kernel on `stream` (grid work-groups of one wave,
+// LDS for primes up to max_p); the counter must hold a.base.
 hipError_t batch_launch(const BatchArgs& a, int grid, int max_p, hipStream_t stream);
 
 // Kernel functions, for graph nodes.

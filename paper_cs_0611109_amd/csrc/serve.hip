@@ -80,10 +80,10 @@ struct InFlight {
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  BatchJob* h_jobs = nullptr;   // pinned
-  BatchItem* h_items = nullptr; // pinned
-  void* d_mem = nullptr;        // jobs | items | counter
-  size_t cap_jobs = 0, cap_items = 0;
+  uint8_t* h_buf = nullptr;     // pinned: items | jobs of the batch being formed
+  uint8_t* d_mem = nullptr;     // counter (256 bytes) | items | jobs
+  size_t cap = 0;               // bytes of h_buf and of d_mem's table area
+  uint64_t counter = 0;         // value the device counter holds between runs
   std::vector<InFlight> reqs;
   uint64_t launch_ns = 0;
   bool busy = false;      // owns requests
@@ -188,21 +188,26 @@ void complete_one(raid6c_server* s, const raid6c_request& req, uint64_t arrival,
   s->outstanding--;
 }
 
+size_t table_bytes(size_t jobs, size_t items) {
+  return round_up(items * sizeof(BatchItem), 64) + jobs * sizeof(BatchJob);
+}
+
+// Make room for a batch's tables; a new device block starts with a zeroed
+// counter.  Called without the lock, on the slot's stream being idle.
 bool grow_slot(Slot& sl, size_t jobs, size_t items) {
-  if (jobs <= sl.cap_jobs && items <= sl.cap_items) return true;
-  const size_t nj = std::max(jobs, sl.cap_jobs * 2 + 16), ni = std::max(items, sl.cap_items * 2 + 256);
-  if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
-  if (sl.h_items) (void)hipHostFree(sl.h_items);
+  const size_t need = table_bytes(jobs, items);
+  if (need <= sl.cap) return true;
+  const size_t cap = std::max(need, sl.cap * 2 + 65536);
+  if (sl.h_buf) (void)hipHostFree(sl.h_buf);
   if (sl.d_mem) (void)hipFree(sl.d_mem);
-  sl.h_jobs = nullptr;
-  sl.h_items = nullptr;
+  sl.h_buf = nullptr;
   sl.d_mem = nullptr;
-  sl.cap_jobs = sl.cap_items = 0;
-  if (hipHostMalloc((void**)&sl.h_jobs, nj * sizeof(BatchJob), 0) != hipSuccess) return false;
-  if (hipHostMalloc((void**)&sl.h_items, ni * sizeof(BatchItem), 0) != hipSuccess) return false;
-  if (hipMalloc(&sl.d_mem, nj * sizeof(BatchJob) + ni * sizeof(BatchItem) + 256) != hipSuccess) return false;
-  sl.cap_jobs = nj;
-  sl.cap_items = ni;
+  sl.cap = 0;
+  if (hipHostMalloc((void**)&sl.h_buf, cap, 0) != hipSuccess) return false;
+  if (hipMalloc((void**)&sl.d_mem, cap + 256) != hipSuccess) return false;
+  if (hipMemsetAsync(sl.d_mem, 0, 256, sl.stream) != hipSuccess) return false;
+  sl.counter = 0;
+  sl.cap = cap;
   return true;
 }
 
@@ -226,11 +231,16 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     return hipEventRecord(sl.done, sl.stream);
   }
   size_t nitems = 0;
+  for (const InFlight& f : sl.reqs) nitems += (f.stripe->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
+  const size_t jobs_off = round_up(nitems * sizeof(BatchItem), 64);
+  BatchItem* h_items = (BatchItem*)sl.h_buf;
+  BatchJob* h_jobs = (BatchJob*)(sl.h_buf + jobs_off);
+  nitems = 0;
   for (size_t i = 0; i < sl.reqs.size(); ++i) {
     const InFlight& f = sl.reqs[i];
     const Resident* st = f.stripe;
     const size_t strip = (size_t)(st->p - 1) * st->row_bytes;
-    BatchJob& j = sl.h_jobs[i];
+    BatchJob& j = h_jobs[i];
     memset(&j, 0, sizeof j);
     j.base = s->store + st->off;
     j.strip_stride = strip;
@@ -255,24 +265,25 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
       j.e1 = (int16_t)hi;
       j.out1 = (uint8_t*)f.req.dst + strip;
     }
-    for (uint32_t c = 0; c < st->row_bytes; c += kBatchTileBytes) sl.h_items[nitems++] = BatchItem{(uint32_t)i, c};
+    for (uint32_t c = 0; c < st->row_bytes; c += kBatchTileBytes) h_items[nitems++] = BatchItem{(uint32_t)i, c};
   }
-  BatchJob* d_jobs = (BatchJob*)sl.d_mem;
-  BatchItem* d_items = (BatchItem*)((uint8_t*)sl.d_mem + sl.cap_jobs * sizeof(BatchJob));
-  uint32_t* d_counter = (uint32_t*)((uint8_t*)d_items + sl.cap_items * sizeof(BatchItem));
-  hipError_t e = hipMemcpyAsync(d_jobs, sl.h_jobs, sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, sl.stream);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(d_items, sl.h_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, sl.stream);
+  // One upload for both tables.
+  uint64_t* d_counter = (uint64_t*)sl.d_mem;
+  uint8_t* d_tab = sl.d_mem + 256;
+  hipError_t e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob),
+                                hipMemcpyHostToDevice, sl.stream);
   if (e != hipSuccess) return e;
   int max_p = 3;
   for (const InFlight& f : sl.reqs) max_p = std::max(max_p, f.stripe->p);
-  BatchArgs a{d_jobs, d_items, (uint32_t)nitems, 4u, d_counter};
+  BatchArgs a{(const BatchJob*)(d_tab + jobs_off), (const BatchItem*)d_tab, (uint32_t)nitems, 4u, d_counter,
+              sl.counter};
   const int waves = s->cfg.waves_per_cu > 0 ? s->cfg.waves_per_cu : 8;
   int grid = s->cus * waves;
   const int need = (int)((nitems + a.chunk - 1) / a.chunk);
   if (need < grid) grid = std::max(1, need);
   e = batch_launch(a, grid, max_p, sl.stream);
   if (e != hipSuccess) return e;
+  sl.counter = batch_counter_after(sl.counter, a.nitems, a.chunk, (uint32_t)grid);
   return hipEventRecord(sl.done, sl.stream);
 }
 
@@ -566,8 +577,7 @@ int raid6c_server_destroy(raid6c_server* s) {
   for (Slot& sl : s->slots) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream && sl.stream != s->plain_stream) (void)hipStreamDestroy(sl.stream);
-    if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
-    if (sl.h_items) (void)hipHostFree(sl.h_items);
+    if (sl.h_buf) (void)hipHostFree(sl.h_buf);
     if (sl.d_mem) (void)hipFree(sl.d_mem);
   }
   if (s->plain_stream) (void)hipStreamDestroy(s->plain_stream);
