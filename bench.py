@@ -318,6 +318,119 @@ def copy_probe(stream, nbytes=1 << 30, reps=3):
     torch.cuda.synchronize()
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries.  The three runs below (from the repository root, on one
+# MI355X) produce the CSV folders that --summarize turns into the committed
+# text summaries and the traffic table read by lookup_traffic().
+PROFILE_CMDS = {
+    "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_stats -o run -- "
+             "python -u bench.py --steps 10 --warmup 2 --no-cpu-baseline --no-extras",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o run -- "
+             "python -u bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-probe",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o run -- "
+             "python -u bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-probe",
+}
+WORKLOAD_TAG = f"zp_p{P}_k{K}_w{W}_x{NSTRIPES}"
+
+
+def _short_name(name: str) -> str:
+    import re
+    m = re.search(r"(zp_\w+_kernel<[^>]*>)", name)
+    if m:
+        return m.group(1)
+    if "direct_copy_kernel" in name:
+        return "torch direct_copy (host->device staging of the input)"
+    if "FillFunctor" in name or "fill_kernel" in name:
+        return "torch fill"
+    return name[:60]
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(stats_dir: str, fetch_dir: str, write_dir: str, out_dir: str = None) -> dict:
+    """Turn the three rocprofv3 runs of PROFILE_CMDS into the kernel-statistics
+    and HBM-byte summaries and the traffic table (host-only; no GPU)."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    strip = (P - 1) * W
+    alg = (K + 2) * strip * NSTRIPES
+    head = (f"workload: p={P}, k={K}, W={W} B rows, {NSTRIPES} stripes "
+            f"({K * strip * NSTRIPES / 2**30:.2f} GiB user data); one step = one encode launch + one "
+            f"recovery launch (per-stripe pair uniform over the {(K + 2) * (K + 1) // 2} strip pairs); "
+            "launch configurations from paper_cs_0611109_amd/tuned_mi355x.json")
+
+    rows = _read_csv(os.path.join(stats_dir, "run_kernel_stats.csv"))
+    lines = ["# rocprofv3 kernel statistics: Z_p-RAID encode + two-erasure recovery", "# " + head,
+             "# command (from the repository root, on one MI355X):", "#   " + PROFILE_CMDS["stats"],
+             "# source: run_kernel_stats.csv (durations in ns)", "",
+             f"{'kernel':<56}{'calls':>6}{'avg_ns':>11}{'min_ns':>10}{'max_ns':>10}{'pct':>7}"]
+    avg = {}
+    for r_ in rows:
+        n = _short_name(r_["Name"])
+        lines.append(f"{n:<56}{int(r_['Calls']):>6}{float(r_['AverageNs']):>11.0f}{int(r_['MinNs']):>10}"
+                     f"{int(r_['MaxNs']):>10}{float(r_['Percentage']):>7.2f}")
+        if n.startswith("zp_"):
+            avg[n] = float(r_["AverageNs"])
+    lines += ["", f"algorithmic bytes per launch (both kernels): (k+2)(p-1)W x stripes = {alg} B"]
+    for n, ns in avg.items():
+        gbs = alg / ns
+        lines.append(f"{n}: {gbs:.1f} GB/s = {gbs / HBM_PEAK_GBPS:.4f} of the 8 TB/s HBM peak")
+    with open(os.path.join(out_dir, f"{WORKLOAD_TAG}_kernel_stats.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def per_kernel(d, counter):
+        got, wg, copies = {}, {}, []
+        for r_ in _read_csv(os.path.join(d, "run_counter_collection.csv")):
+            if r_["Counter_Name"] != counter:
+                continue
+            v = float(r_["Counter_Value"])
+            if "copyBuffer" in r_["Kernel_Name"]:
+                if v > 100000:          # the 1 GiB probe copies, not small staging copies
+                    copies.append(v)
+                continue
+            n = _short_name(r_["Kernel_Name"])
+            if n.startswith("zp_"):
+                got.setdefault(n, []).append(v)
+                wg[n] = int(r_["Workgroup_Size"])
+        if len(copies) < 1:
+            raise RuntimeError(f"{d}: no 1 GiB probe copy found (run with --copy-probe)")
+        return {n: sum(v) / len(v) for n, v in got.items()}, wg, sum(copies) / len(copies)
+
+    fetch, wg, cf = per_kernel(fetch_dir, "FETCH_SIZE")
+    write, _, cw = per_kernel(write_dir, "WRITE_SIZE")
+    fs, ws = 2**30 / (cf * 1024), 2**30 / (cw * 1024)
+    lines = [f"# rocprofv3 HBM byte counters: Z_p-RAID kernels, p={P} k={K} W={W} B x {NSTRIPES} stripes",
+             "# commands (one counter per run, from the repository root, on one MI355X):",
+             "#   " + PROFILE_CMDS["fetch"], "#   " + PROFILE_CMDS["write"],
+             "# --copy-probe adds three plain 1 GiB device-to-device copies (the runtime's copyBuffer",
+             "# kernel) whose counter readings give the scale from counter KiB to bytes moved.", "",
+             f"copy_1GiB FETCH_SIZE avg {cf:.0f} KiB -> fetch scale {fs:.4f} (bytes per counted byte)",
+             f"copy_1GiB WRITE_SIZE avg {cw:.0f} KiB -> write scale {ws:.4f}", ""]
+    table, digest = {}, source_digest()
+    import re
+    for n in sorted(fetch):
+        if n not in write:
+            continue
+        hbm = int(round(fetch[n] * 1024 * fs + write[n] * 1024 * ws))
+        lines.append(f"{n}: FETCH_SIZE {fetch[n]:.0f} KiB, WRITE_SIZE {write[n]:.0f} KiB per launch -> "
+                     f"{hbm} B scaled HBM traffic; algorithmic {alg} B; ratio {hbm / alg:.5f}")
+        m = re.match(r"zp_\w+_kernel<(\d+), (\d+), (\d+)>", n)
+        key = n.replace(", ", ",")
+        table[key] = {"source_sha256": digest, "config": [int(m.group(2)), int(m.group(3)), wg[n]],
+                      "algorithmic_bytes": alg, "hbm_bytes_per_launch": hbm,
+                      "fetch_kib": round(fetch[n]), "write_kib": round(write[n]),
+                      "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+                      "summary": f"profiles/{WORKLOAD_TAG}_hbm_bytes.txt"}
+    with open(os.path.join(out_dir, f"{WORKLOAD_TAG}_hbm_bytes.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(out_dir, "traffic.json"), "w") as f:
+        json.dump(table, f, indent=1)
+    return table
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,7 +443,12 @@ def main():
                     help="time every launch configuration for this geometry first (else use the tuning cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 1 GiB device copies (for scaling HBM byte counters)")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summaries from the three rocprofv3 runs (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize:
+        print(json.dumps(summarize_profiles(*args.summarize), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (stripes are independent, "
               "so more GPUs would shard stripes with no communication; see the design notes).",
