@@ -84,6 +84,62 @@ def inv_one_plus_g_power(v: np.ndarray, z: int, p: int) -> np.ndarray:
     return acc
 
 
+def poly_mod(a: int, m: int) -> int:
+    """Remainder of ``a`` modulo ``m`` in F2[X]; a polynomial is an int whose
+    bit i is the coefficient of X^i."""
+    if m == 0:
+        raise ZeroDivisionError("polynomial modulus is zero")
+    dm = m.bit_length()
+    while a.bit_length() >= dm:
+        a ^= m << (a.bit_length() - dm)
+    return a
+
+
+def poly_gcd(a: int, b: int) -> int:
+    """Greatest common divisor in F2[X] (Euclid's algorithm)."""
+    while b:
+        a, b = b, poly_mod(a, b)
+    return a
+
+
+def extension_ok(p: int) -> bool:
+    """Condition (3) of Theorem 3.3.3: for every 0 < m < p the polynomials
+    X^p + 1 and X^m + X + 1 are relatively prime over F2.  Exactly then the
+    2p-1 matrices g^i and Id + g^j form a cone, so the extended Q parity of
+    Section 3.3 protects up to 2p-1 data strips."""
+    check_prime(p)
+    xp1 = (1 << p) | 1
+    return all(poly_gcd(xp1, (1 << m) ^ 0b10 ^ 1) == 1 for m in range(1, p))
+
+
+def gf2_inverse(m: np.ndarray) -> np.ndarray:
+    """Inverse of a square GF(2) matrix by Gauss-Jordan elimination; raises
+    ValueError when it is singular."""
+    n = m.shape[0]
+    a = np.concatenate([m & 1, np.eye(n, dtype=np.uint8)], axis=1).astype(np.uint8)
+    for c in range(n):
+        rows = [r for r in range(c, n) if a[r, c]]
+        if not rows:
+            raise ValueError("singular matrix")
+        if rows[0] != c:
+            a[[c, rows[0]]] = a[[rows[0], c]]
+        for r in range(n):
+            if r != c and a[r, c]:
+                a[r] ^= a[c]
+    return a[:, n:]
+
+
+def apply_matrix(m: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """``m . v`` for a GF(2) matrix acting on the rows of ``v`` (row r of the
+    result is the XOR of the rows c of ``v`` with m[r, c] = 1)."""
+    out = np.zeros_like(v)
+    for r in range(m.shape[0]):
+        for c in range(m.shape[1]):
+            if m[r, c]:
+                out[..., r, :] ^= v[..., c, :]
+    return out
+
+
 def element_from_bits(bits, p: int) -> np.ndarray:
     """One-lane element from a sequence of ``p-1`` bits (row r = bits[r])."""
     arr = np.asarray(bits, dtype=np.uint8).reshape(p - 1, 1)

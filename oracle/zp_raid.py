@@ -15,21 +15,54 @@ the Reed-Solomon parity of Section 4.1)::
 with ``g = S_p`` (Lemma 3.4.1) and ``1 <= k <= p``.  Recovery follows the four
 cases of the proof of Lemma 3.1.2; the two-data case uses the formulas of
 Sections 4.3 and 4.6.  The input contents of erased strips are never read.
+
+Extended Q parity (Section 3.3, eq. *qext*): for primes that satisfy
+Theorem 3.3.3, up to ``2p - 1`` data strips are allowed, and strip
+``t >= p`` enters Q with the coefficient ``Id + g^{t-p+1}``::
+
+    Q = sum_{t < p} g^t D_t + sum_{t >= p} (Id + g^{t-p+1}) D_t
+
+For ``k <= p`` this is the code above.  A recovery that involves a strip
+``t >= p`` uses the general formulas of the proof of Lemma 3.1.2, with the
+inverse of the coefficient (or of the sum of two coefficients) taken by
+GF(2) elimination of its matrix: the paper gives no closed form for these.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
-from .ring import (check_prime, inv_one_plus_g_power, mul_g_power, sylvester_step)
+from .ring import (apply_matrix, check_prime, extension_ok, gf2_inverse, inv_one_plus_g_power, matrix_of,
+                   mul_g_power, sylvester_step)
+
+
+def max_data_strips(p: int) -> int:
+    """``2p - 1`` when the extended cone of Theorem 3.3.3 exists for ``p``,
+    else ``p`` (Corollary 3.2.4)."""
+    check_prime(p)
+    return 2 * p - 1 if extension_ok(p) else p
 
 
 def _check(p: int, k: int, rows: int) -> None:
     check_prime(p)
-    if not 1 <= k <= p:
-        raise ValueError(f"k = {k} must satisfy 1 <= k <= p = {p}")
+    if not 1 <= k <= p and not (p < k <= max_data_strips(p)):
+        raise ValueError(f"k = {k} must satisfy 1 <= k <= p = {p} "
+                         f"(or <= 2p-1 where Theorem 3.3.3 holds)")
     if rows != p - 1:
         raise ValueError("strips must have p-1 rows")
+
+
+def coefficient(v: np.ndarray, t: int, p: int) -> np.ndarray:
+    """``g_t . v``: ``g^t v`` for ``t < p``, ``v + g^{t-p+1} v`` for ``t >= p``
+    (eq. *qext*)."""
+    if t < p:
+        return mul_g_power(v, t, p)
+    return v ^ mul_g_power(v, t - p + 1, p)
+
+
+def _solve(fn, v: np.ndarray, p: int) -> np.ndarray:
+    """``M^{-1} v`` where ``M`` is the matrix of the linear map ``fn``."""
+    return apply_matrix(gf2_inverse(matrix_of(fn, p)), v)
 
 
 def p_parity(data: np.ndarray, skip=()) -> np.ndarray:
@@ -42,18 +75,22 @@ def p_parity(data: np.ndarray, skip=()) -> np.ndarray:
 
 
 def q_parity(data: np.ndarray, p: int, skip=()) -> np.ndarray:
-    """``sum_t g^t D_t`` over the data strips not in ``skip``.
+    """``sum_t g_t D_t`` over the data strips not in ``skip``.
 
     Horner's rule of Section 4.2, ``Q = D_0 + g(D_1 + g(... + g D_{k-1}))``,
-    with the strips in ``skip`` taken as zero; with the two failed strips
-    skipped this is the syndrome ``Q_xy`` of Section 4.3.
+    over the strips ``t < p``, with the strips in ``skip`` taken as zero; with
+    the two failed strips skipped this is the syndrome ``Q_xy`` of Section
+    4.3.  Strips ``t >= p`` (extended parity) add ``(Id + g^{t-p+1}) D_t``.
     """
     k = data.shape[-3]
     acc = np.zeros(data.shape[:-3] + data.shape[-2:], dtype=np.uint8)
-    for t in range(k - 1, -1, -1):
+    for t in range(min(k, p) - 1, -1, -1):
         acc = sylvester_step(acc, p)
         if t not in skip:
             acc ^= data[..., t, :, :]
+    for t in range(p, k):
+        if t not in skip:
+            acc ^= coefficient(data[..., t, :, :], t, p)
     return acc
 
 
@@ -125,16 +162,26 @@ def recover(stripe: np.ndarray, p: int, erased) -> np.ndarray:
         out[..., iQ, :, :] = q_parity(data, p)
     elif y == iP:                      # data x and P
         t = Q ^ q_parity(data, p, skip)
-        out[..., x, :, :] = mul_g_power(t, p - x, p)
+        if x < p:
+            out[..., x, :, :] = mul_g_power(t, p - x, p)
+        else:                          # D_x = g_x^{-1} (Q + sum_{t != x} g_t D_t)
+            out[..., x, :, :] = _solve(lambda v: coefficient(v, x, p), t, p)
         out[..., iP, :, :] = p_parity(out[..., :k, :, :])
     elif y == iQ:                      # data x and Q
         out[..., x, :, :] = P ^ p_parity(data, skip)
         out[..., iQ, :, :] = q_parity(out[..., :k, :, :], p)
-    else:                              # two data strips x < y
+    elif y < p:                        # two data strips x < y < p
         z = y - x
         dP = P ^ p_parity(data, skip)
         dQ = Q ^ q_parity(data, p, skip)
         dy = inv_one_plus_g_power(dP, z, p) ^ mul_g_power(inv_one_plus_g_power(dQ, z, p), p - x, p)
+        out[..., y, :, :] = dy
+        out[..., x, :, :] = dy ^ dP
+    else:                              # two data strips, y >= p (extended parity)
+        # Lemma 3.1.2: D_y = (g_x + g_y)^{-1} (g_x dP + dQ), then D_x = D_y + dP.
+        dP = P ^ p_parity(data, skip)
+        dQ = Q ^ q_parity(data, p, skip)
+        dy = _solve(lambda v: coefficient(v, x, p) ^ coefficient(v, y, p), coefficient(dP, x, p) ^ dQ, p)
         out[..., y, :, :] = dy
         out[..., x, :, :] = dy ^ dP
     return out

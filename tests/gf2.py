@@ -89,13 +89,14 @@ def parity_check_matrix(p, k):
 def _parity_check_matrix(p, k):
     """The parity-check matrix of Corollary 3.2.4 with g = S_p, for k data
     strips: block rows [I .. I I 0] and [I g .. g^{k-1} 0 I], block columns in
-    strip order D_0 .. D_{k-1}, P, Q."""
+    strip order D_0 .. D_{k-1}, P, Q.  For k > p the blocks of strips t >= p
+    are I + g^{t-p+1} (extended Q parity, eq. qext of Section 3.3)."""
     n = p - 1
     g = sylvester_matrix(p)
     h = np.zeros((2 * n, (k + 2) * n), dtype=np.uint8)
     for t in range(k):
         h[:n, t * n:(t + 1) * n] = identity(n)
-        h[n:, t * n:(t + 1) * n] = power(g, t)
+        h[n:, t * n:(t + 1) * n] = power(g, t) if t < p else identity(n) ^ power(g, t - p + 1)
     h[:n, k * n:(k + 1) * n] = identity(n)
     h[n:, (k + 1) * n:(k + 2) * n] = identity(n)
     return h

@@ -259,7 +259,9 @@ def test_argument_checks():
     with pytest.raises(ValueError):
         zp.encode(np.zeros((2, 8, 4), np.uint8), 9)         # 9 is not prime
     with pytest.raises(ValueError):
-        zp.encode(np.zeros((6, 4, 4), np.uint8), 5)         # k > p
+        zp.encode(np.zeros((10, 4, 4), np.uint8), 5)        # k > 2p-1
+    with pytest.raises(ValueError):
+        zp.encode(np.zeros((8, 6, 4), np.uint8), 7)         # k > p, and p = 7 has no extended cone
     with pytest.raises(ValueError):
         zp.encode(np.zeros((2, 3, 4), np.uint8), 5)         # wrong row count
     st = zp.encode_stripe(np.zeros((3, 4, 4), np.uint8), 5)
