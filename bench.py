@@ -89,7 +89,10 @@ def fill_batch(batch, seed, chunk=256):
 
 
 def time_launches(fn, reps, stream):
+    """HIP-event durations of `reps` calls of `fn` on `stream`, after one
+    untimed call."""
     import torch
+    fn()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for a, b in evs:
         a.record(stream)
@@ -188,8 +191,44 @@ def extras(reps, stream):
     out["p29_k28_w1024_x8192"] = res
     del b
     torch.cuda.empty_cache()
+    out["extended_q_parity"] = extended(reps, stream)
     out["batched_20000_mixed"] = batched_mixed(reps, stream)
     out["served_poisson"] = served_poisson()
+    return out
+
+
+def extended(reps, stream):
+    """Extended Q parity (Section 3.3, k = 2p-1 data strips): encode, and
+    recovery of a pair uniform over all pairs and of each class that the
+    plain code does not have (plain + extended data, which takes the
+    trinomial inverse; two extended data strips; extended data + P / Q).
+    Bytes moved per launch (k+2)(p-1)W per stripe, as for the plain code."""
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    out = {}
+    for p, w, n in ((13, 4096, 2048), (29, 1024, 4096)):
+        k = 2 * p - 1
+        b = r.StripeBatch.empty(p, k, w, n)
+        b.tensor[:, :k].random_(0, 256)
+        moved = (k + 2) * b.strip_stride * n
+
+        def entry(ms):
+            mean = sum(ms) / len(ms)
+            return {"GBps_user": round(b.user_bytes / (mean / 1e3) / 1e9, 1),
+                    "hbm_frac": round(moved / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                    "ms_p50": round(pct(ms, 50), 4)}
+
+        res = {"encode": entry(time_launches(lambda: b.encode(), reps, stream))}
+        kinds = [("any", datagen.erasures(6, n, k, "any"))]
+        kinds += [(kd, datagen.erasures_extended(6, n, k, p, kd)) for kd in datagen.EXTENDED_ERASURE_KINDS]
+        for kd, er_host in kinds:
+            er = torch.from_numpy(er_host).to("cuda:0")
+            res[kd] = entry(time_launches(lambda: b.recover(er), reps, stream))
+        out[f"p{p}_k{k}_w{w}_x{n}"] = res
+        del b
+        torch.cuda.empty_cache()
     return out
 
 

@@ -176,6 +176,43 @@ def erasures(seed: int, nstripes: int, k: int, kind: str) -> np.ndarray:
     return out
 
 
+EXTENDED_ERASURE_KINDS = ("dd_mixed", "dd_ext", "dp_ext", "dq_ext")
+
+
+def erasures_extended(seed: int, nstripes: int, k: int, p: int, kind: str) -> np.ndarray:
+    """Erasure pairs of one class of a stripe with extended Q parity
+    (``p < k <= 2p-1``; strips ``t >= p`` are the extended ones), shape
+    ``(nstripes, 2)`` int32, sorted:
+
+    * ``dd_mixed``: data ``x < p`` and extended data ``y >= p``, uniform.
+    * ``dd_ext``: two extended data strips, uniform (needs ``k >= p+2``).
+    * ``dp_ext`` / ``dq_ext``: an extended data strip, uniform, plus P / Q.
+    """
+    if kind not in EXTENDED_ERASURE_KINDS:
+        raise ValueError(f"unknown extended erasure kind {kind!r}")
+    if not p < k <= 2 * p - 1:
+        raise ValueError("needs p < k <= 2p-1")
+    d = Draws(seed, TAG_ERASURE, 64 + EXTENDED_ERASURE_KINDS.index(kind))
+    m = k - p                         # extended strips p .. k-1
+    out = np.empty((nstripes, 2), dtype=np.int32)
+    for s in range(nstripes):
+        if kind == "dd_mixed":
+            pair = (d.below(p), p + d.below(m))
+        elif kind == "dd_ext":
+            if m < 2:
+                raise ValueError("dd_ext needs two extended strips")
+            a = d.below(m)
+            b = d.below(m - 1)
+            b += b >= a
+            pair = (p + min(a, b), p + max(a, b))
+        elif kind == "dp_ext":
+            pair = (p + d.below(m), k)
+        else:
+            pair = (p + d.below(m), k + 1)
+        out[s] = pair
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Mixed-geometry workloads (batched and served forms)
 # ---------------------------------------------------------------------------

@@ -12,6 +12,16 @@
  * 1 <= k <= p data strips.  Any one or two strips of a stripe can be rebuilt
  * from the others (Lemma 3.1.2).
  *
+ * Extended Q parity (Section 3.3, eq. qext): for primes that satisfy
+ * Theorem 3.3.3 (all supported primes except the Mersenne primes 3, 7, 31),
+ * up to 2p-1 data strips, strip t >= p entering Q with 1 + g^{t-p+1}:
+ *
+ *   Q = sum_{t<p} g^t D_t + sum_{t>=p} (1 + g^{t-p+1}) D_t
+ *
+ * For k <= p this is the code above.  The single-stripe and strided entry
+ * points, writes and degraded reads accept k up to raid6c_max_data_strips(p);
+ * plans and the request server run k <= p only.
+ *
  * Layout.  A strip is p-1 rows of row_bytes bytes, row r at byte offset
  * r*row_bytes; bit b of byte j of row r is the coefficient of x^r of lane
  * (j, b), so every lane is an independent ring element.  A stripe is k data
@@ -56,6 +66,13 @@ int raid6c_max_prime(void);
 /* 1 when p is an odd prime <= raid6c_max_prime(), else 0. */
 int raid6c_is_supported_prime(int p);
 
+/* Largest number of data strips k for prime p: 2p-1 when p satisfies
+ * condition (3) of Theorem 3.3.3 (X^p + 1 and X^m + X + 1 coprime over F2
+ * for 0 < m < p), so that the extended Q parity exists; p otherwise.
+ * Errors: RAID6C_E_ARG if p is not an odd prime; RAID6C_E_UNSUPPORTED if
+ * p > raid6c_max_prime(). */
+int raid6c_max_data_strips(int p);
+
 /* Static text for a RAID6C_* code. */
 const char* raid6c_strerror(int code);
 
@@ -70,8 +87,10 @@ const char* raid6c_last_error(void);
  * 0-based indexing of the Reed-Solomon parity of Section 4.1).
  *   data : host array of k device pointers, data[t] = strip D_t (read only)
  *   P, Q : device strips written with the parities
- * Errors: RAID6C_E_ARG if p is not an odd prime, k not in [1, p], row_bytes
- * not a positive multiple of 16, or a pointer NULL or misaligned;
+ * With k > p the parity is the extended one (eq. qext).
+ * Errors: RAID6C_E_ARG if p is not an odd prime, k not in
+ * [1, raid6c_max_data_strips(p)], row_bytes not a positive multiple of 16,
+ * or a pointer NULL or misaligned;
  * RAID6C_E_UNSUPPORTED if p > raid6c_max_prime(). */
 int raid6c_encode(int p, int k, size_t row_bytes, const void* const* data,
                   void* P, void* Q, void* stream);

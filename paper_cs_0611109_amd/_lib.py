@@ -28,6 +28,7 @@ _i32p = ctypes.c_void_p
 SIGNATURES = {
     "raid6c_max_prime": (_c_int, []),
     "raid6c_is_supported_prime": (_c_int, [_c_int]),
+    "raid6c_max_data_strips": (_c_int, [_c_int]),
     "raid6c_strerror": (ctypes.c_char_p, [_c_int]),
     "raid6c_last_error": (ctypes.c_char_p, []),
     "raid6c_encode": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _vp, _vp, _vp]),
@@ -187,6 +188,14 @@ def raid6c_max_prime() -> int:
 
 def raid6c_is_supported_prime(p: int) -> bool:
     return bool(load().raid6c_is_supported_prime(p))
+
+
+def raid6c_max_data_strips(p: int) -> int:
+    """2p-1 where the extended Q parity exists (Theorem 3.3.3), else p."""
+    rc = load().raid6c_max_data_strips(p)
+    if rc < 0:
+        _check(rc)
+    return rc
 
 
 def raid6c_strerror(code: int) -> str:

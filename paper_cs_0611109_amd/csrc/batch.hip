@@ -50,7 +50,7 @@ __device__ __forceinline__ void run_item(const BatchJob& j, uint32_t col, uint32
   const ColsJob c{j.base, j.strip_stride, j.out0, j.out1, j.src, j.src_stride, j.e0, j.e1,
                   j.row_bytes, col, (uint32_t)((P - 1) * j.row_bytes)};
   const Case cs{j.op, j.x, j.y};
-  tile_recover<P, 1, batch_unroll(P)>(c, j.k, cs, lds, kLanes);
+  tile_recover<P, 1, batch_unroll(P), false>(c, j.k, cs, lds, kLanes);
 }
 
 __global__ void reset_counter(uint64_t* counter) { *counter = 0ull; }
@@ -213,6 +213,8 @@ int check_job(const raid6c_job& J, size_t i, Case* out) {
   const int p = J.p, k = J.k;
   if (!is_odd_prime(p)) return fail(RAID6C_E_ARG, "job %zu: p = %d is not an odd prime", i, p);
   if (p > kMaxPrime) return fail(RAID6C_E_UNSUPPORTED, "job %zu: p = %d is not built", i, p);
+  if (k > p && k < 2 * p)
+    return fail(RAID6C_E_UNSUPPORTED, "job %zu: k = %d > p: plans run the plain code only (k <= p)", i, k);
   if (k < 1 || k > p) return fail(RAID6C_E_ARG, "job %zu: k = %d not in [1, %d]", i, k, p);
   if (J.row_bytes == 0 || (J.row_bytes % 16) != 0)
     return fail(RAID6C_E_ARG, "job %zu: row_bytes must be a positive multiple of 16", i);

@@ -55,12 +55,54 @@ static bool is_odd_prime(int p) {
 
 static bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 
+// F2[X] polynomials of degree < 64 as bit masks (bit i = coefficient of X^i).
+static int poly_deg(uint64_t a) { return 63 - __builtin_clzll(a); }
+
+static uint64_t poly_rem(uint64_t a, uint64_t m) {
+  const int dm = poly_deg(m);
+  while (a != 0 && poly_deg(a) >= dm) a ^= m << (poly_deg(a) - dm);
+  return a;
+}
+
+static uint64_t poly_gcd(uint64_t a, uint64_t b) {
+  while (b != 0) {
+    const uint64_t r = poly_rem(a, b);
+    a = b;
+    b = r;
+  }
+  return a;
+}
+
+// Theorem 3.3.3, condition (3): for every 0 < m < p, X^p + 1 and X^m + X + 1
+// are relatively prime over F2.  Exactly then the 2p-1 elements x^i and
+// 1 + x^j form a cone and the extended Q parity protects 2p-1 data strips.
+// (p <= kMaxPrime = 61, so X^p + 1 fits in 64 bits.)
+static bool extension_ok(int p) {
+  const uint64_t xp1 = (1ull << p) | 1ull;
+  for (int m = 1; m < p; ++m)
+    if (poly_gcd(xp1, (1ull << m) ^ 2ull ^ 1ull) != 1ull) return false;
+  return true;
+}
+
+// Largest k for a supported prime: 2p-1 with the extended Q parity, else p.
+static int max_data(int p) {
+  static const auto table = [] {
+    struct T { int k[kMaxPrime + 1]; } t{};
+    for (int q = 3; q <= kMaxPrime; q += 2)
+      if (is_odd_prime(q)) t.k[q] = extension_ok(q) ? 2 * q - 1 : q;
+    return t;
+  }();
+  return table.k[p];
+}
+
 // Common checks of p, k and the row size.
 int check_geometry(int p, int k, size_t row_bytes) {
   if (!is_odd_prime(p)) return fail(RAID6C_E_ARG, "p = %d is not an odd prime", p);
   if (p > kMaxPrime)
     return fail(RAID6C_E_UNSUPPORTED, "p = %d exceeds the largest built prime %d", p, kMaxPrime);
-  if (k < 1 || k > p) return fail(RAID6C_E_ARG, "k = %d must satisfy 1 <= k <= p = %d", k, p);
+  if (k < 1 || k > max_data(p))
+    return fail(RAID6C_E_ARG, "k = %d must satisfy 1 <= k <= %d for p = %d%s", k, max_data(p), p,
+                max_data(p) == p ? " (p fails Theorem 3.3.3: no extended Q parity)" : "");
   if (row_bytes == 0 || (row_bytes % 16) != 0)
     return fail(RAID6C_E_ARG, "row_bytes = %zu must be a positive multiple of 16", row_bytes);
   if ((size_t)(p - 1) * row_bytes >= ((size_t)1 << 31))
@@ -124,7 +166,8 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
       if (a.erasures != nullptr) b.erasures = a.erasures + 2 * done;
     }
     b.nstripes = (uint32_t)n;
-    const hipError_t err = e->launch(kind, cfg, b, (uint32_t)(n * a.tiles), (hipStream_t)stream);
+    const ZpLauncher fn = a.k > p ? e->launch_ext : e->launch;
+    const hipError_t err = fn(kind, cfg, b, (uint32_t)(n * a.tiles), (hipStream_t)stream);
     if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     done += n;
   }
@@ -152,6 +195,13 @@ extern "C" {
 int raid6c_max_prime(void) { return kMaxPrime; }
 
 int raid6c_is_supported_prime(int p) { return (is_odd_prime(p) && p <= kMaxPrime) ? 1 : 0; }
+
+int raid6c_max_data_strips(int p) {
+  g_last_error.clear();
+  if (!is_odd_prime(p)) return fail(RAID6C_E_ARG, "p = %d is not an odd prime", p);
+  if (p > kMaxPrime) return fail(RAID6C_E_UNSUPPORTED, "p = %d exceeds the largest built prime %d", p, kMaxPrime);
+  return max_data(p);
+}
 
 const char* raid6c_strerror(int code) {
   switch (code) {

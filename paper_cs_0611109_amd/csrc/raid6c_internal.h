@@ -10,7 +10,9 @@ namespace raid6c {
 
 // Largest prime built into the GPU path (odd primes 3..61).
 constexpr int kMaxPrime = 61;
-constexpr int kMaxStrips = kMaxPrime + 2;  // k <= p data strips + P + Q
+// Up to 2p-1 data strips with the extended Q parity (Section 3.3), + P + Q.
+constexpr int kMaxData = 2 * kMaxPrime - 1;
+constexpr int kMaxStrips = kMaxData + 2;
 
 // Cases of Lemma 3.1.2 (plus the single erasures and plain encode).
 enum : int {
@@ -77,14 +79,15 @@ struct ZpConfig {
 
 enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
 
-// Per-prime launchers, one translation unit per prime (zp_kernels.hip).
+// Per-prime launchers, two translation units per prime (zp_kernels.hip).
 // Return hipSuccess or the launch error (hipErrorInvalidValue for a
 // configuration that is not built).
 typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a,
                                  uint32_t grid, hipStream_t stream);
 struct ZpPrimeEntry {
   int p;
-  ZpLauncher launch;
+  ZpLauncher launch;       // plain code, k <= p
+  ZpLauncher launch_ext;   // extended Q parity, p < k <= 2p-1
   int vec_mask;        // bit v set when vec = v is instantiated (bits 1, 2, 4)
   int unroll_mask[5];  // per vec: bit u set when (vec, unroll = u) is instantiated
 

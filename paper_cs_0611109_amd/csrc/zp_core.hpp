@@ -160,14 +160,33 @@ struct ColsJob {
   __device__ __forceinline__ uint64_t W() const { return row_bytes; }
 };
 
+// Row r of a strip: the row offset r*W is the same for the whole wave and is
+// the scalar offset operand of the buffer instruction.  With
+// RAID6C_UNIFORM_ROW_HINT, readfirstlane states that it is uniform: in the
+// extended-parity kernels the compiler otherwise keeps such offsets in
+// vector registers and wraps every access in a loop over the distinct
+// values.  (Elsewhere the hint is not needed, and in the persistent kernel
+// it makes compilation very slow.)
+#ifndef RAID6C_UNIFORM_ROW_HINT
+#define RAID6C_UNIFORM_ROW_HINT 0
+#endif
+__device__ __forceinline__ uint32_t row_offset(int r, uint64_t W) {
+  const uint32_t o = (uint32_t)r * (uint32_t)W;
+#if RAID6C_UNIFORM_ROW_HINT
+  return __builtin_amdgcn_readfirstlane(o);
+#else
+  return o;
+#endif
+}
+
 template <typename VT>
 __device__ __forceinline__ VT ld(__amdgpu_buffer_rsrc_t s, int r, uint64_t W, uint32_t col) {
-  return bufio<sizeof(VT) / 4>::load(s, col, (uint32_t)r * (uint32_t)W);
+  return bufio<sizeof(VT) / 4>::load(s, col, row_offset(r, W));
 }
 
 template <typename VT>
 __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t s, int r, uint64_t W, uint32_t col, VT v) {
-  bufio<sizeof(VT) / 4>::store(v, s, col, (uint32_t)r * (uint32_t)W);
+  bufio<sizeof(VT) / 4>::store(v, s, col, row_offset(r, W));
 }
 
 // acc_q <- x * acc_q in C: a cyclic shift of the p rows (register renaming).
@@ -179,19 +198,24 @@ __device__ __forceinline__ void rotate_up(VT (&aq)[P]) {
   aq[0] = top;
 }
 
-// Streaming phase over the data strips, skipping strips x and y (-1 = none).
-// HP: accumulate acc_p; HQ: accumulate acc_q (Horner in C).  The strips are
-// taken U at a time: the U*(p-1) row loads of a batch are all issued before
-// the first of them is used, so each thread keeps U*(p-1) loads in flight.
+// Streaming over the data strips hi down to lo, skipping strips x and y
+// (-1 = none).  HP: accumulate acc_p; HQ: accumulate acc_q (Horner in C).
+// The strips are taken U at a time: the U*(p-1) row loads of a batch are all
+// issued before the first of them is used, so each thread keeps U*(p-1)
+// loads in flight.
 template <int P, int V, int U, bool HP, bool HQ, class C>
-__device__ __forceinline__ void stream_data(const C& c, int k, int x, int y,
-                                            typename vec_t<V>::type (&ap)[P - 1],
-                                            typename vec_t<V>::type (&aq)[P]) {
+__device__ __forceinline__ void stream_range(const C& c, int hi, int lo, int x, int y,
+                                             typename vec_t<V>::type (&ap)[P - 1],
+                                             typename vec_t<V>::type (&aq)[P]) {
   typedef typename vec_t<V>::type VT;
   constexpr int R = P - 1;
   const uint64_t W = c.W();
-  int t = k - 1;
-  for (; t >= U - 1; t -= U) {
+  int t = hi;
+  // Never unrolled: with constant bounds (the p strips below p of an
+  // extended stripe) the compiler would otherwise hoist every load of the
+  // range at once.
+#pragma unroll 1
+  for (; t >= lo + U - 1; t -= U) {
     __builtin_amdgcn_sched_barrier(0);
     VT v[U][R];
 #pragma unroll
@@ -228,7 +252,8 @@ __device__ __forceinline__ void stream_data(const C& c, int k, int x, int y,
       }
     }
   }
-  for (; t >= 0; --t) {
+#pragma unroll 1
+  for (; t >= lo; --t) {
     if (HQ) rotate_up<P>(aq);
     __builtin_amdgcn_sched_barrier(0);
     if (t == x || t == y) continue;
@@ -250,6 +275,31 @@ __device__ __forceinline__ void stream_data(const C& c, int k, int x, int y,
   }
 }
 
+// The whole streaming phase over data strips k-1 .. 0.
+//  * Plain code (EXT false, k <= p): one Horner pass.
+//  * Extended Q parity (EXT true, p < k <= 2p-1; Section 3.3, eq. qext):
+//    strip t >= p enters Q with 1 + x^{t-p+1}.  A Horner pass over those
+//    strips leaves A = sum_{t>=p} x^{t-p} D_t in acc_q while acc_p collects
+//    B = sum_{t>=p} D_t; then acc_q <- x A + B, and the pass over the p
+//    strips t < p multiplies that by x^p = 1 (in C) while adding
+//    sum_{t<p} x^t D_t.  acc_p must start at zero in this case.
+template <int P, int V, int U, bool HP, bool HQ, bool EXT, class C>
+__device__ __forceinline__ void stream_data(const C& c, int k, int x, int y,
+                                            typename vec_t<V>::type (&ap)[P - 1],
+                                            typename vec_t<V>::type (&aq)[P]) {
+  if constexpr (!EXT) {
+    stream_range<P, V, U, HP, HQ>(c, k - 1, 0, x, y, ap, aq);
+  } else {
+    stream_range<P, V, U, HP || HQ, HQ>(c, k - 1, P, x, y, ap, aq);
+    if (HQ) {
+      rotate_up<P>(aq);
+#pragma unroll
+      for (int r = 0; r < P - 1; ++r) aq[r] ^= ap[r];
+    }
+    stream_range<P, V, U, HP, HQ>(c, P - 1, 0, x, y, ap, aq);
+  }
+}
+
 template <int P, int V, class C>
 __device__ __forceinline__ void load_into(const C& c, int j, typename vec_t<V>::type (&acc)[P - 1]) {
   typedef typename vec_t<V>::type VT;
@@ -260,8 +310,9 @@ __device__ __forceinline__ void load_into(const C& c, int j, typename vec_t<V>::
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int P, int V, class C>
-__device__ __forceinline__ void xor_from(const C& c, int j, typename vec_t<V>::type (&acc)[P]) {
+// acc[r] ^= strip j row r, r < p-1 (acc has p-1 or p entries).
+template <int P, int V, int N, class C>
+__device__ __forceinline__ void xor_from(const C& c, int j, typename vec_t<V>::type (&acc)[N]) {
   typedef typename vec_t<V>::type VT;
   const __amdgpu_buffer_rsrc_t b = c.strip(j);
   const uint64_t W = c.W();
@@ -295,7 +346,7 @@ __device__ __forceinline__ void store_reduced(const C& c, int j, const typename 
 }
 
 // Full encode of one tile: P and Q (either may be skipped).
-template <int P, int V, int U, class C>
+template <int P, int V, int U, bool EXT, class C>
 __device__ __forceinline__ void tile_encode(const C& c, int k, bool wp, bool wq) {
   typedef typename vec_t<V>::type VT;
   VT ap[P - 1], aq[P];
@@ -304,11 +355,11 @@ __device__ __forceinline__ void tile_encode(const C& c, int k, bool wp, bool wq)
 #pragma unroll
   for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
   if (wp && wq) {
-    stream_data<P, V, U, true, true>(c, k, -1, -1, ap, aq);
+    stream_data<P, V, U, true, true, EXT>(c, k, -1, -1, ap, aq);
   } else if (wp) {
-    stream_data<P, V, U, true, false>(c, k, -1, -1, ap, aq);
+    stream_data<P, V, U, true, false, EXT>(c, k, -1, -1, ap, aq);
   } else {
-    stream_data<P, V, U, false, true>(c, k, -1, -1, ap, aq);
+    stream_data<P, V, U, false, true, EXT>(c, k, -1, -1, ap, aq);
   }
   if (wp) store_strip<P, V>(c, k, ap);
   if (wq) store_reduced<P, V>(c, k + 1, aq);
@@ -326,11 +377,79 @@ template <int V> struct comp {
   static __device__ __forceinline__ void set(VT& v, int c, uint32_t x) { v[c] = x; }
 };
 
+// Solve (1 + x^z) D = T for one dword column held in LDS (rows 0..p-1 of a
+// lift T~ of T), in place: the chain described at the top of this file, with
+// e the XOR of all p rows of T~.  Afterwards the column holds D~ with
+// D~[p-1] = 0, i.e. rows 0..p-2 are D.
+template <int P>
+__device__ __forceinline__ void chain_solve(uint32_t* lds, int ls, int z, uint32_t e) {
+  constexpr int R = P - 1;
+  // Rows u_s = (p-1 + s z) mod p, s = 1..p-1; each row is visited once.  The
+  // next row's value is read before the current one is written: rows of
+  // consecutive steps differ, so the read does not see the write.
+  int u = R + z;
+  if (u >= P) u -= P;
+  uint32_t t = lds[u * ls];
+  uint32_t d = 0u;
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    int un = u + z;
+    if (un >= P) un -= P;
+    const uint32_t tn = (s + 1 < R) ? lds[un * ls] : 0u;
+    d = t ^ e ^ d;
+    lds[u * ls] = d;
+    t = tn;
+    u = un;
+  }
+}
+
+// Inverse of f in R_p = F2[x]/(1 + x + ... + x^{p-1}); polynomials are bit
+// masks (bit i = coefficient of x^i).  Extended Euclid against
+// Phi_p = 1 + x + ... + x^{p-1}, keeping s with s*f = r (mod Phi_p); ends when
+// r = 1 and returns s, of degree < p-1.  The arguments are uniform over the
+// wave, so this runs on the scalar unit.  Every step lowers deg r, so the
+// loops end after at most 64 rounds even for a non-invertible f (which the
+// host's checks exclude).
+__device__ __forceinline__ uint64_t inverse_mod_phi(uint64_t f, int p) {
+  const uint64_t phi = (1ull << p) - 1ull;
+  if ((f >> (p - 1)) & 1ull) f ^= phi;
+  uint64_t r0 = phi, r1 = f, s0 = 0ull, s1 = 1ull;
+  while (r1 > 1ull) {
+    const int d1 = 63 - __builtin_clzll(r1);
+    int d0 = 63 - __builtin_clzll(r0);
+    while (d0 >= d1) {
+      r0 ^= r1 << (d0 - d1);
+      s0 ^= s1 << (d0 - d1);
+      if (r0 == 0ull) break;
+      d0 = 63 - __builtin_clzll(r0);
+    }
+    const uint64_t tr = r0, ts = s0;
+    r0 = r1;
+    s0 = s1;
+    r1 = tr;
+    s1 = ts;
+  }
+  return s1;
+}
+
 // Recovery of one tile.  `lds` points at this thread's column of a region of
 // P rows of one dword, row stride `ls` dwords; only this thread touches it.
 // The data-dependent row permutations are done one dword column at a time,
 // so the region does not grow with the vector width.
-template <int P, int V, int U, class C>
+//
+// EXT: the stripe has k > p data strips and the extended Q parity of
+// Section 3.3 (coefficient g_t = x^t for t < p, 1 + x^{t-p+1} for t >= p).
+// The general recovery formulas of the proof of Lemma 3.1.2 then read
+//   data x + P:  g_x D_x = dQ,
+//   data x + Q:  D_x = dP, Q = (Q sum without x) + g_x D_x,
+//   data x < y:  (g_x + g_y) D_y = g_x dP + dQ,  D_x = D_y + dP,
+// with dP, dQ the syndromes of the surviving strips.  g_x + g_y is
+// x^x (1 + x^{y-x}) when both are below p, x^i (1 + x^{j-i}) when both are
+// extended (i = x-p+1, j = y-p+1), both solved by the chain; for x < p <= y
+// it is the trinomial 1 + x^x + x^j, whose inverse h (Theorem 3.3.3 makes it
+// exist) is computed per wave and applied as the cyclic convolution
+// D~[u] = sum_{i in h} G~[u - i] in C.
+template <int P, int V, int U, bool EXT, class C>
 __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_in, uint32_t* lds, int ls) {
   typedef typename vec_t<V>::type VT;
   typedef comp<V> CP;
@@ -343,13 +462,13 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
 
   switch (cs.op) {
     case OP_PQ:
-      tile_encode<P, V, U>(c, k, true, true);
+      tile_encode<P, V, U, EXT>(c, k, true, true);
       return;
     case OP_P:
-      tile_encode<P, V, U>(c, k, true, false);
+      tile_encode<P, V, U, EXT>(c, k, true, false);
       return;
     case OP_Q:
-      tile_encode<P, V, U>(c, k, false, true);
+      tile_encode<P, V, U, EXT>(c, k, false, true);
       return;
     default:
       break;
@@ -362,28 +481,47 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
   if (cs.op == OP_D) {
     // D_x = P + sum_{t != x} D_t.
     load_into<P, V>(c, iP, ap);
-    stream_data<P, V, U, true, false>(c, k, cs.x, -1, ap, aq);
+    stream_range<P, V, U, true, false>(c, k - 1, 0, cs.x, -1, ap, aq);
     store_strip<P, V>(c, cs.x, ap);
     return;
   }
 
+  // dP (with P itself, as the recovery needs it) in ap, dQ~ (without Q) in
+  // aq.  With extended parity acc_p must start at zero, so P comes last.
+  auto syndromes = [&](int x, int y) {
+    if constexpr (EXT) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
+      stream_data<P, V, U, true, true, true>(c, k, x, y, ap, aq);
+      xor_from<P, V>(c, iP, ap);
+    } else {
+      load_into<P, V>(c, iP, ap);
+      stream_data<P, V, U, true, true, false>(c, k, x, y, ap, aq);
+    }
+  };
+
   if (cs.op == OP_DQ) {
-    // D_x = P + sum_{t != x} D_t;  Q = sum_{t != x} x^t D_t + x^x D_x.
+    // D_x = dP;  Q = sum_{t != x} g_t D_t + g_x D_x.
     const int x = cs.x;
-    load_into<P, V>(c, iP, ap);
-    stream_data<P, V, U, true, true>(c, k, x, -1, ap, aq);
+    const bool xe = EXT && x >= P;        // g_x = 1 + x^{sh}, else x^{sh}
+    const int sh = xe ? x - P + 1 : x;
+    syndromes(x, -1);
 #pragma unroll
     for (int cc = 0; cc < V; ++cc) {
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[r * ls] = CP::get(ap[r], cc);
       lds[R * ls] = 0u;
-      // (x^x D~)[u] = D~[(u - x) mod p]
+      // (x^sh D~)[u] = D~[(u - sh) mod p]
 #pragma unroll
       for (int u = 0; u < P; ++u) {
-        int w = u - x;
+        int w = u - sh;
         if (w < 0) w += P;
         CP::set(aq[u], cc, CP::get(aq[u], cc) ^ lds[w * ls]);
       }
+    }
+    if (xe) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) aq[r] ^= ap[r];
     }
     store_strip<P, V>(c, x, ap);
     store_reduced<P, V>(c, iQ, aq);
@@ -391,13 +529,38 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
   }
 
   if (cs.op == OP_DP) {
-    // D_x = x^{p-x} (Q + sum_{t != x} x^t D_t);  P = sum_{t != x} D_t + D_x.
+    // g_x D_x = Q + sum_{t != x} g_t D_t;  P = sum_{t != x} D_t + D_x.
     const int x = cs.x;
 #pragma unroll
     for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
-    stream_data<P, V, U, true, true>(c, k, x, -1, ap, aq);
+    stream_data<P, V, U, true, true, EXT>(c, k, x, -1, ap, aq);
     xor_from<P, V>(c, iQ, aq);
-    // (x^{p-x} a)[u] = a[(u + x) mod p], in place.
+    if (EXT && x >= P) {
+      // (1 + x^j) D_x = dQ, j = x-p+1: the chain on the lift dQ~.
+      const int j = x - P + 1;
+#pragma unroll
+      for (int cc = 0; cc < V; ++cc) {
+        uint32_t e = 0u;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+          const uint32_t t = CP::get(aq[u], cc);
+          lds[u * ls] = t;
+          e ^= t;
+        }
+        chain_solve<P>(lds, ls, j, e);
+#pragma unroll
+        for (int r = 0; r < R; ++r) CP::set(aq[r], cc, lds[r * ls]);
+      }
+      const __amdgpu_buffer_rsrc_t bx = c.strip(x), bp = c.strip(iP);
+      const uint64_t W = c.W();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        st<VT>(bx, r, W, c.col, aq[r]);
+        st<VT>(bp, r, W, c.col, aq[r] ^ ap[r]);
+      }
+      return;
+    }
+    // D_x = x^{p-x} dQ:  (x^{p-x} a)[u] = a[(u + x) mod p], in place.
 #pragma unroll
     for (int cc = 0; cc < V; ++cc) {
 #pragma unroll
@@ -421,58 +584,79 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
     return;
   }
 
-  // OP_DD: data x < y, z = y - x.
-  //   dP = P + sum_{t != x,y} D_t,  dQ~ = Q + sum_{t != x,y} x^t D_t (in C),
-  //   T~ = dP~ + x^{p-x} dQ~,  (1 + x^z) D_y = T,  D_x = D_y + dP.
-  const int x = cs.x;
-  const int z = cs.y - cs.x;
-  load_into<P, V>(c, iP, ap);
-  stream_data<P, V, U, true, true>(c, k, cs.x, cs.y, ap, aq);
+  // OP_DD: data x < y.
+  const int x = cs.x, y = cs.y;
+  syndromes(x, y);
   xor_from<P, V>(c, iQ, aq);
 
+  if (EXT && x < P && y >= P) {
+    // (1 + x^x + x^j) D_y = x^x dP + dQ =: G, j = y-p+1.  (x = 0 gives x^j,
+    // x = j gives 1; the inverse covers both.)
+    const int j = y - P + 1;
+    const uint64_t h = inverse_mod_phi((1ull << x) ^ (1ull << j) ^ 1ull, P);
 #pragma unroll
-  for (int cc = 0; cc < V; ++cc) {
-    // T~[u] = dP~[u] + dQ~[(u + x) mod p], built in aq (natural row order).
+    for (int cc = 0; cc < V; ++cc) {
 #pragma unroll
-    for (int u = 0; u < P; ++u) lds[u * ls] = CP::get(aq[u], cc);
-    uint32_t e = 0u;  // XOR of all p rows of T~
+      for (int r = 0; r < R; ++r) lds[r * ls] = CP::get(ap[r], cc);
+      lds[R * ls] = 0u;
+      uint32_t g[P];
 #pragma unroll
-    for (int u = 0; u < P; ++u) {
-      int w = u + x;
-      if (w >= P) w -= P;
-      uint32_t t = lds[w * ls];
-      if (u < R) t ^= CP::get(ap[u], cc);
-      e ^= t;
-      CP::set(aq[u], cc, t);
-    }
-#pragma unroll
-    for (int u = 0; u < P; ++u) lds[u * ls] = CP::get(aq[u], cc);
-    // Chain over rows u_s = (p-1 + s z) mod p, s = 1..p-1:
-    // D~[u_s] = T~[u_s] + e + D~[u_{s-1}], D~[p-1] = 0, written in place (each
-    // row is visited once, so its T~ value is read before it is replaced).
-    // The next row's value is read before the current one is written: rows
-    // of consecutive steps differ, so the read does not see the write.
-    {
-      int u = R + z;
-      if (u >= P) u -= P;
-      uint32_t t = lds[u * ls];
-      uint32_t d = 0u;
-#pragma unroll
-      for (int s = 0; s < R; ++s) {
-        int un = u + z;
-        if (un >= P) un -= P;
-        const uint32_t tn = (s + 1 < R) ? lds[un * ls] : 0u;
-        d = t ^ e ^ d;
-        lds[u * ls] = d;
-        t = tn;
-        u = un;
+      for (int u = 0; u < P; ++u) {
+        int w = u - x;
+        if (w < 0) w += P;
+        g[u] = CP::get(aq[u], cc) ^ lds[w * ls];
       }
-    }
-    // D_y in natural row order back into aq.
 #pragma unroll
-    for (int r = 0; r < R; ++r) CP::set(aq[r], cc, lds[r * ls]);
+      for (int u = 0; u < P; ++u) lds[u * ls] = g[u];
+#pragma unroll
+      for (int u = 0; u < P; ++u) g[u] = 0u;
+      for (uint64_t m = h; m != 0ull; m &= m - 1ull) {
+        const int i = __builtin_ctzll(m) % P;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+          int w = u - i;
+          if (w < 0) w += P;
+          g[u] ^= lds[w * ls];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) CP::set(aq[r], cc, g[r] ^ g[R]);
+    }
+  } else {
+    // (1 + x^z) D_y = T with T = dP + x^{-s} dQ', where
+    //   both below p:    s = x,      z = y - x, dQ' = dQ;
+    //   both extended:   s = x-p+1,  z = y - x, dQ' = dQ + dP.
+    const bool both_ext = EXT && x >= P;
+    const int s = both_ext ? x - P + 1 : x;
+    const int z = y - x;
+    if (both_ext) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) aq[r] ^= ap[r];
+    }
+#pragma unroll
+    for (int cc = 0; cc < V; ++cc) {
+      // T~[u] = dP~[u] + dQ'~[(u + s) mod p], built in aq (natural row order).
+#pragma unroll
+      for (int u = 0; u < P; ++u) lds[u * ls] = CP::get(aq[u], cc);
+      uint32_t e = 0u;  // XOR of all p rows of T~
+#pragma unroll
+      for (int u = 0; u < P; ++u) {
+        int w = u + s;
+        if (w >= P) w -= P;
+        uint32_t t = lds[w * ls];
+        if (u < R) t ^= CP::get(ap[u], cc);
+        e ^= t;
+        CP::set(aq[u], cc, t);
+      }
+#pragma unroll
+      for (int u = 0; u < P; ++u) lds[u * ls] = CP::get(aq[u], cc);
+      chain_solve<P>(lds, ls, z, e);
+      // D_y in natural row order back into aq.
+#pragma unroll
+      for (int r = 0; r < R; ++r) CP::set(aq[r], cc, lds[r * ls]);
+    }
   }
-  const __amdgpu_buffer_rsrc_t bx = c.strip(cs.x), by = c.strip(cs.y);
+  const __amdgpu_buffer_rsrc_t bx = c.strip(x), by = c.strip(y);
   const uint64_t W = c.W();
 #pragma unroll
   for (int r = 0; r < R; ++r) {

@@ -1,12 +1,19 @@
 // zp_kernels.hip -- Z_p-RAID encode and recovery kernels for one prime.
 //
-// This file is compiled once per supported prime with -DRAID6C_P=<p>; each
-// object contributes one launcher to the dispatch table of the host API.
+// This file is compiled twice per supported prime, with -DRAID6C_P=<p> and
+// -DRAID6C_EXT=0 or 1: the plain code (k <= p) and the extended Q parity
+// (p < k <= 2p-1, Section 3.3) go to separate objects, so that the code of
+// one never shapes the compiler's choices for the other.  Each pair of
+// objects contributes one entry to the dispatch table of the host API.
 //
 // Grid: one work-group per (stripe, column tile); a tile is `threads` threads
 // times V dwords of every row.  Work-group i handles stripe i / tiles and tile
 // i % tiles, so the stripe and its erasure case are uniform over the group and
 // all strip addresses live in scalar registers.
+#ifndef RAID6C_EXT
+#define RAID6C_EXT 0
+#endif
+#define RAID6C_UNIFORM_ROW_HINT RAID6C_EXT
 #include "zp_core.hpp"
 
 #ifndef RAID6C_P
@@ -21,13 +28,15 @@ namespace raid6c {
 namespace {
 
 constexpr int kP = RAID6C_P;
+constexpr bool kExt = RAID6C_EXT != 0;
 static_assert(kP >= 3 && kP <= kMaxPrime && (kP % 2) == 1, "unsupported prime");
 
 // Vector widths built for this prime: wider vectors need (2p-1)*V registers
 // for the two accumulators, so they are only built for small p.
 constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (kP <= 31) ? (1 | 2) : 1;
 
-template <int P, int V, int U>
+// EXT: k > p data strips with the extended Q parity of Section 3.3.
+template <int P, int V, int U, bool EXT>
 __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
   const uint32_t stripe = blockIdx.x / a.tiles;
   const uint32_t tile = blockIdx.x - stripe * a.tiles;
@@ -35,10 +44,10 @@ __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
   if (col >= a.row_bytes) return;
   const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
                     (uint32_t)((P - 1) * a.row_bytes)};
-  tile_encode<P, V, U>(c, a.k, true, true);
+  tile_encode<P, V, U, EXT>(c, a.k, true, true);
 }
 
-template <int P, int V, int U>
+template <int P, int V, int U, bool EXT>
 __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t stripe = blockIdx.x / a.tiles;
@@ -59,7 +68,7 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   if (col >= a.row_bytes) return;
   const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, 0, col, (uint32_t)((P - 1) * a.row_bytes)};
   uint32_t* lds = reinterpret_cast<uint32_t*>(smem) + threadIdx.x;
-  tile_recover<P, V, U>(c, a.k, cs, lds, (int)blockDim.x);
+  tile_recover<P, V, U, EXT>(c, a.k, cs, lds, (int)blockDim.x);
 }
 
 // (vec, unroll) pairs built for this prime: accumulators take (2p-1)*vec
@@ -81,12 +90,10 @@ hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t
                      hipStream_t stream) {
   if constexpr (built<V, U>()) {
     const dim3 g(grid), b(cfg.threads);
-    if (kind == KIND_ENCODE) {
-      hipLaunchKernelGGL((zp_encode_kernel<kP, V, U>), g, b, 0, stream, a);
-    } else {
-      const size_t lds = (size_t)kP * cfg.threads * 4;
-      hipLaunchKernelGGL((zp_recover_kernel<kP, V, U>), g, b, lds, stream, a);
-    }
+    const size_t lds = (size_t)kP * cfg.threads * 4;
+    if ((a.k > kP) != kExt) return hipErrorInvalidValue;
+    if (kind == KIND_ENCODE) hipLaunchKernelGGL((zp_encode_kernel<kP, V, U, kExt>), g, b, 0, stream, a);
+    else hipLaunchKernelGGL((zp_recover_kernel<kP, V, U, kExt>), g, b, lds, stream, a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -111,9 +118,20 @@ hipError_t launch(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t gr
 
 }  // namespace
 
+#if RAID6C_EXT
+hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                                                hipStream_t stream) {
+  return launch(kind, cfg, a, grid, stream);
+}
+#else
+hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                                                hipStream_t stream);
+
 const ZpPrimeEntry* RAID6C_CAT(zp_entry_, RAID6C_P)() {
-  static const ZpPrimeEntry e{kP, &launch, kVecMask, {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)}};
+  static const ZpPrimeEntry e{kP, &launch, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
+                              {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)}};
   return &e;
 }
+#endif
 
 }  // namespace raid6c

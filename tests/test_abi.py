@@ -45,6 +45,21 @@ def test_prime_support():
         assert (r.raid6c_vec_mask(p) != 0) == r.raid6c_is_supported_prime(p)
 
 
+def test_max_data_strips_follows_theorem_333():
+    # 2p-1 data strips exactly where the extended cone exists (the oracle's
+    # reading of Theorem 3.3.3): every supported prime but 3, 7 and 31.
+    from oracle import ring
+    for p in range(3, r.raid6c_max_prime() + 1, 2):
+        if not r.raid6c_is_supported_prime(p):
+            continue
+        want = 2 * p - 1 if ring.extension_ok(p) else p
+        assert r.raid6c_max_data_strips(p) == want, p
+    assert [p for p in range(3, 62, 2) if r.raid6c_is_supported_prime(p) and r.raid6c_max_data_strips(p) == p] \
+        == [3, 7, 31]
+    _err(r.raid6c_max_data_strips, 9)
+    _err(r.raid6c_max_data_strips, 67, code=r.RAID6C_E_UNSUPPORTED)
+
+
 def _err(fn, *args, code=r.RAID6C_E_ARG, **kw):
     with pytest.raises(r.Raid6cError) as ei:
         fn(*args, **kw)
@@ -68,7 +83,8 @@ def test_encode_n_argument_checks():
     _err(call, p=2)
     _err(call, p=67, code=r.RAID6C_E_UNSUPPORTED)
     _err(call, k=0)
-    _err(call, k=6)
+    _err(call, k=10, stripe_stride=12 * 256)      # k > 2p-1
+    _err(call, p=7, k=8, row_bytes=16, strip_stride=96, stripe_stride=10 * 96)   # p = 7: no extended parity
     _err(call, row_bytes=0)
     _err(call, row_bytes=24)
     _err(call, base=0)
@@ -148,7 +164,7 @@ def test_plan_rejects_bad_jobs_before_device_work():
     good = J(0, 5, 4, -1, -1, 64, 256, FAKE)
     cases = [
         J(0, 9, 4, -1, -1, 64, 256, FAKE),            # not prime
-        J(0, 5, 6, -1, -1, 64, 256, FAKE),            # k > p
+        J(0, 5, 10, -1, -1, 64, 256, FAKE),           # k > 2p-1
         J(0, 5, 4, -1, -1, 24, 256, FAKE),            # row bytes
         J(0, 5, 4, -1, -1, 64, 255, FAKE),            # stride
         J(0, 5, 4, -1, -1, 64, 256, FAKE + 8),        # alignment
@@ -160,5 +176,7 @@ def test_plan_rejects_bad_jobs_before_device_work():
         _err(r.raid6c_plan_create, [bad])
         _err(r.raid6c_plan_create, [good, bad])
     _err(r.raid6c_plan_create, [J(0, 67, 4, -1, -1, 64, 66 * 64, FAKE)], code=r.RAID6C_E_UNSUPPORTED)
+    # extended Q parity (k > p) is not run by plans
+    _err(r.raid6c_plan_create, [J(0, 5, 6, -1, -1, 64, 256, FAKE)], code=r.RAID6C_E_UNSUPPORTED)
     # two jobs sharing bytes
     _err(r.raid6c_plan_create, [J(0, 5, 4, -1, -1, 64, 256, FAKE), J(0, 5, 4, -1, -1, 64, 256, FAKE + 1024)])

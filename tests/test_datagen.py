@@ -80,3 +80,22 @@ def test_serve_requests_ranges():
             assert reqs[r.target].kind == "write" and r.target < r.index
             assert 0 <= r.e0 < r.k
             assert r.e1 == -1 or r.e0 < r.e1 < r.k + 2
+
+
+@pytest.mark.parametrize("kind", datagen.EXTENDED_ERASURE_KINDS)
+def test_extended_erasures_stay_in_their_class(kind):
+    p, k = 13, 25
+    e = datagen.erasures_extended(3, 3000, k, p, kind)
+    assert e.shape == (3000, 2) and e.dtype == np.int32
+    assert (e[:, 0] < e[:, 1]).all()
+    x, y = e[:, 0], e[:, 1]
+    if kind == "dd_mixed":
+        assert (x < p).all() and (y >= p).all() and (y < k).all()
+        assert len(set(map(tuple, e))) == p * (k - p)          # every mixed pair occurs
+    elif kind == "dd_ext":
+        assert (x >= p).all() and (y < k).all()
+    elif kind == "dp_ext":
+        assert (x >= p).all() and (x < k).all() and (y == k).all()
+    else:
+        assert (x >= p).all() and (x < k).all() and (y == k + 1).all()
+    assert np.array_equal(e, datagen.erasures_extended(3, 3000, k, p, kind))
