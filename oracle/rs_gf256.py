@@ -99,3 +99,57 @@ def recover_two_data(stripe: np.ndarray, x: int, y: int) -> np.ndarray:
     out[..., y, :] = dy
     out[..., x, :] = dy ^ dP
     return out
+
+
+def recover(stripe: np.ndarray, erased) -> np.ndarray:
+    """Rebuild one or two erased disks (indices ``0 .. N+1``; ``N`` = P,
+    ``N+1`` = Q) of an RS stripe ``(..., N+2, n)``, by the cases of the proof
+    of Lemma 3.1.2 with the cone ``{g^t}`` of Section 4.1:
+
+    * P and Q, P alone, Q alone: recompute from the data.
+    * one data disk ``x``: ``D_x = P + P_x`` (RAID-5 parity).
+    * data ``x`` and P: ``D_x = g^{-x} (Q + Q_x)``, then ``P``.
+    * data ``x`` and Q: ``D_x = P + P_x``, then ``Q``.
+    * data ``x < y``: Sections 4.3 and 4.4 (``recover_two_data``).
+
+    ``P_x``, ``Q_x`` are the syndromes with the erased disks taken as zero.
+    ``g^{-x}`` is the inverse of ``g^x``, found by search.
+    """
+    n_disks = stripe.shape[-2] - 2
+    er = sorted(set(int(e) for e in erased))
+    if len(er) != len(tuple(erased)) or not 1 <= len(er) <= 2:
+        raise ValueError("need one or two distinct erased disks")
+    if any(e < 0 or e > n_disks + 1 for e in er):
+        raise ValueError("erased index out of range")
+    iP, iQ = n_disks, n_disks + 1
+    out = stripe.copy()
+    data = out[..., :n_disks, :].copy()
+    for e in er:
+        if e < n_disks:
+            data[..., e, :] = 0
+    px, qx = encode(data)                 # syndromes without the erased data disks
+    if len(er) == 1:
+        e = er[0]
+        if e < n_disks:
+            out[..., e, :] = out[..., iP, :] ^ px
+        elif e == iP:
+            out[..., iP, :] = px
+        else:
+            out[..., iQ, :] = qx
+        return out
+    x, y = er
+    if (x, y) == (iP, iQ):
+        out[..., iP, :] = px
+        out[..., iQ, :] = qx
+    elif y == iP:
+        dx = gf_mul_const(out[..., iQ, :] ^ qx, gf_inv(gf_pow2(x)))
+        out[..., x, :] = dx
+        out[..., iP, :] = px ^ dx
+    elif y == iQ:
+        dx = out[..., iP, :] ^ px
+        out[..., x, :] = dx
+        out[..., iQ, :] = qx ^ gf_mul_const(dx, gf_pow2(x))
+    else:
+        out = recover_two_data(out, x, y)
+    return out
+
