@@ -166,6 +166,20 @@ def extras(reps, stream):
     }
     zp_ms = time_launches(lambda: b.encode(), reps, stream)
     out["zp_encode_same_bytes_ms_p50"] = round(pct(zp_ms, 50), 4)
+    # Recovery by case, RS against Z_p on the same geometry (the shape of the
+    # paper's DD / DP / PQ reconstruction table; timings do not depend on the
+    # byte values).
+    cmp_ = {}
+    for kind in ("dd", "dp", "dq", "pq"):
+        er = torch.from_numpy(datagen.erasures(2, NSTRIPES, K, kind)).to("cuda:0")
+        rs_ms = time_launches(lambda: b.rs_recover(er), reps, stream)
+        zp_ms = time_launches(lambda: b.recover(er), reps, stream)
+        cmp_[kind] = {"rs_ms_p50": round(pct(rs_ms, 50), 4), "zp_ms_p50": round(pct(zp_ms, 50), 4),
+                      "rs_GBps_user": round(b.user_bytes / (pct(rs_ms, 50) / 1e3) / 1e9, 1),
+                      "zp_GBps_user": round(b.user_bytes / (pct(zp_ms, 50) / 1e3) / 1e9, 1)}
+    cmp_["paper_p4_time_units"] = {"dd": {"rs": 2917, "z17": 2711}, "dp": {"rs": 2771, "z17": 1274},
+                                   "pq": {"rs": 905, "z17": 809}}
+    out["rs_vs_zp_recovery"] = cmp_
     del b
     torch.cuda.empty_cache()
 

@@ -175,7 +175,7 @@ int raid6c_read_degraded(int p, int k, size_t row_bytes, const void* const* stri
                          void* out, void* stream);
 
 /* ------------------------------------------------------------------------
- * Comparison code: Reed-Solomon P+Q over GF(256), polynomial 0x11D
+ * Comparison code: Reed-Solomon RAID-6 over GF(256), polynomial 0x11D
  * ------------------------------------------------------------------------ */
 
 /* Encode nstripes Reed-Solomon stripes (Section 4.1):
@@ -188,6 +188,29 @@ int raid6c_read_degraded(int p, int k, size_t row_bytes, const void* const* stri
 int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base,
                        size_t strip_stride, size_t stripe_stride, size_t nstripes,
                        void* stream);
+
+/* Rebuild, per Reed-Solomon stripe, the one or two disks named by
+ * erasures[2s], erasures[2s+1] (device int32, 2*nstripes entries; second
+ * entry -1 = single erasure; indices 0..k-1 data, k = P, k+1 = Q), by the
+ * cases of Lemma 3.1.2 for the cone {g^t}:
+ *   data x + P:  D_x = g^{-x} (Q + Q_x), then P;
+ *   data x + Q:  D_x = P + P_x, then Q;
+ *   data x < y:  D_y = A (P + P_xy) + B (Q + Q_xy), D_x = D_y + P + P_xy with
+ *                A = (1 + g^{y-x})^{-1}, B = (g^x + g^y)^{-1} (Sections 4.3-4.4);
+ *   P and/or Q alone, one data disk: recomputed / RAID-5 parity.
+ * Layout and errors as raid6c_rs_encode_n, plus RAID6C_E_ARG if erasures is
+ * NULL or misaligned.  Invalid entries are skipped and counted into
+ * *bad_count (device int32, may be NULL), as in raid6c_recover_n; only the
+ * erased disks are written. */
+int raid6c_rs_recover_n(int k, size_t strip_bytes, void* base,
+                        size_t strip_stride, size_t stripe_stride, size_t nstripes,
+                        const int32_t* erasures, int32_t* bad_count, void* stream);
+
+/* Fix the launch configuration of the Reed-Solomon kernels for this process
+ * (vec dwords per thread: 1, 2, 4; unroll strips loaded together: 1, 4, 8;
+ * threads: 64, 128, 256); (0, 0, 0) restores the built-in rule.
+ * Errors: RAID6C_E_ARG for a configuration that is not built. */
+int raid6c_rs_set_config(int vec, int unroll, int threads);
 
 /* ------------------------------------------------------------------------
  * Plans: many stripes of mixed p, k and row size in one persistent launch

@@ -37,6 +37,8 @@ SIGNATURES = {
     "raid6c_encode_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
     "raid6c_recover_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _i32p, _i32p, _vp]),
     "raid6c_rs_encode_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
+    "raid6c_rs_recover_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp, _vp, _vp]),
+    "raid6c_rs_set_config": (_c_int, [_c_int, _c_int, _c_int]),
     "raid6c_write": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, ctypes.POINTER(_vp), _vp]),
     "raid6c_read_degraded": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _c_int, _c_int, _vp, _vp]),
     "raid6c_vec_mask": (_c_int, [_c_int]),
@@ -249,6 +251,16 @@ def raid6c_recover_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripe
 def raid6c_rs_encode_n(k, strip_bytes, base, strip_stride, stripe_stride, nstripes, stream=None):
     return _check(load().raid6c_rs_encode_n(k, strip_bytes, _ptr(base), strip_stride, stripe_stride,
                                             nstripes, _stream(stream)))
+
+
+def raid6c_rs_recover_n(k, strip_bytes, base, strip_stride, stripe_stride, nstripes, erasures,
+                        bad_count=None, stream=None):
+    return _check(load().raid6c_rs_recover_n(k, strip_bytes, _ptr(base), strip_stride, stripe_stride, nstripes,
+                                             _ptr(erasures), _ptr(bad_count), _stream(stream)))
+
+
+def raid6c_rs_set_config(vec: int, unroll: int, threads: int) -> int:
+    return _check(load().raid6c_rs_set_config(vec, unroll, threads))
 
 
 def raid6c_vec_mask(p: int) -> int:

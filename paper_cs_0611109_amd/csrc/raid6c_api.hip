@@ -352,11 +352,11 @@ int raid6c_recover_n(int p, int k, size_t row_bytes, void* base, size_t strip_st
   return launch_zp(p, KIND_RECOVER, a, nstripes, stream);
 }
 
-int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base, size_t strip_stride, size_t stripe_stride,
-                       size_t nstripes, void* stream) {
+static int rs_run(int k, size_t strip_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                  size_t nstripes, const int32_t* erasures, int32_t* bad_count, void* stream) {
   g_last_error.clear();
   if (k < 1 || k > 255) return fail(RAID6C_E_ARG, "k = %d must satisfy 1 <= k <= 255", k);
-  if (strip_bytes == 0 || (strip_bytes % 16) != 0 || strip_bytes > ((size_t)1 << 31))
+  if (strip_bytes == 0 || (strip_bytes % 16) != 0 || strip_bytes >= ((size_t)1 << 31))
     return fail(RAID6C_E_ARG, "strip_bytes = %zu must be a positive multiple of 16 below 2 GiB", strip_bytes);
   if (nstripes == 0) return RAID6C_OK;
   if (base == nullptr || !aligned16(base)) return fail(RAID6C_E_ARG, "base is NULL or not 16-byte aligned");
@@ -365,12 +365,16 @@ int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base, size_t strip_strid
   if (nstripes > 1 && ((stripe_stride % 16) != 0 || stripe_stride < (size_t)(k + 2) * strip_stride))
     return fail(RAID6C_E_ARG, "stripe_stride must be a multiple of 16 and >= (k+2)*strip_stride");
   if (nstripes > 0xFFFFFFFFull) return fail(RAID6C_E_ARG, "nstripes exceeds 2^32-1");
-  const RsConfig cfg = choose_rs_config(strip_bytes);
+  if (erasures != nullptr && ((uintptr_t)erasures & 3u) != 0)
+    return fail(RAID6C_E_ARG, "erasures must be 4-byte aligned");
+  const RsConfig cfg = choose_rs_config(strip_bytes, erasures != nullptr);
   RsArgs a;
+  memset(&a, 0, sizeof a);
   a.strip_stride = strip_stride;
   a.stripe_stride = stripe_stride;
   a.strip_bytes = strip_bytes;
   a.k = k;
+  a.bad_count = bad_count;
   const uint64_t tile_bytes = (uint64_t)cfg.threads * cfg.vec * 4;
   a.tiles = (uint32_t)((strip_bytes + tile_bytes - 1) / tile_bytes);
   const uint64_t chunk = (((uint64_t)1 << 31) / cfg.threads) / a.tiles;
@@ -378,12 +382,35 @@ int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base, size_t strip_strid
   while (done < nstripes) {
     const size_t n = (nstripes - done) < chunk ? (nstripes - done) : chunk;
     a.base = (uint8_t*)base + done * stripe_stride;
+    a.erasures = erasures != nullptr ? erasures + 2 * done : nullptr;
     a.nstripes = (uint32_t)n;
-    const hipError_t err = rs_launch(a, cfg.vec, cfg.threads, (uint32_t)(n * a.tiles), (hipStream_t)stream);
+    const hipError_t err =
+        rs_launch(a, cfg.vec, cfg.unroll, cfg.threads, (uint32_t)(n * a.tiles), (hipStream_t)stream);
     if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     done += n;
   }
   return RAID6C_OK;
+}
+
+int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                       size_t nstripes, void* stream) {
+  return rs_run(k, strip_bytes, base, strip_stride, stripe_stride, nstripes, nullptr, nullptr, stream);
+}
+
+int raid6c_rs_set_config(int vec, int unroll, int threads) {
+  g_last_error.clear();
+  if (!set_rs_override(vec, unroll, threads))
+    return fail(RAID6C_E_ARG, "RS configuration (vec %d, unroll %d, threads %d) is not built", vec, unroll, threads);
+  return RAID6C_OK;
+}
+
+int raid6c_rs_recover_n(int k, size_t strip_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                        size_t nstripes, const int32_t* erasures, int32_t* bad_count, void* stream) {
+  if (nstripes != 0 && erasures == nullptr) {
+    g_last_error.clear();
+    return fail(RAID6C_E_ARG, "erasures is NULL");
+  }
+  return rs_run(k, strip_bytes, base, strip_stride, stripe_stride, nstripes, erasures, bad_count, stream);
 }
 
 int raid6c_vec_mask(int p) {

@@ -155,7 +155,9 @@ struct RsArgs {
   uint32_t nstripes;
   uint32_t tiles;
   int32_t k;
+  const int32_t* erasures;  // per-stripe pairs (device), or NULL: encode P and Q
+  int32_t* bad_count;       // device counter of rejected entries, or NULL
 };
-hipError_t rs_launch(const RsArgs& a, int vec, int threads, uint32_t grid, hipStream_t stream);
+hipError_t rs_launch(const RsArgs& a, int vec, int unroll, int threads, uint32_t grid, hipStream_t stream);
 
 }  // namespace raid6c

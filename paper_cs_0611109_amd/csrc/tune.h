@@ -8,8 +8,9 @@
 namespace raid6c {
 
 struct RsConfig {
-  int vec;
-  int threads;
+  int vec;      // dwords per thread: 1, 2 or 4
+  int unroll;   // strips whose loads are issued together: 1, 4 or 8
+  int threads;  // 64, 128 or 256
 };
 
 // Configuration for a Z_p kernel: a tuned entry when one has been recorded
@@ -19,8 +20,10 @@ ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes);
 // The built-in rule alone.
 ZpConfig default_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes);
 
-// Configuration for the GF(256) comparison kernel.
-RsConfig choose_rs_config(uint64_t strip_bytes);
+// Configuration for the GF(256) comparison kernel: the override when one is
+// set, else the built-in rule (environment variables first).
+RsConfig choose_rs_config(uint64_t strip_bytes, bool recovery);
+bool set_rs_override(int vec, int unroll, int threads);  // (0, 0, 0) clears
 
 // Row-size bucket used by the tuning table: floor(log2(row_bytes)), 0..30.
 int row_bucket(uint64_t row_bytes);

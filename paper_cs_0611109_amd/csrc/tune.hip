@@ -95,15 +95,38 @@ ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) {
   return default_config(e, kind, row_bytes);
 }
 
-RsConfig choose_rs_config(uint64_t strip_bytes) {
+static std::atomic<uint32_t> g_rs_override{0};  // vec<<16 | unroll<<12 | threads, 0 = none
+
+bool set_rs_override(int vec, int unroll, int threads) {
+  if (vec == 0 && unroll == 0 && threads == 0) {
+    g_rs_override.store(0);
+    return true;
+  }
+  if ((vec != 1 && vec != 2 && vec != 4) || (unroll != 1 && unroll != 4 && unroll != 8) ||
+      (threads != 64 && threads != 128 && threads != 256))
+    return false;
+  g_rs_override.store(((uint32_t)vec << 16) | ((uint32_t)unroll << 12) | (uint32_t)threads);
+  return true;
+}
+
+RsConfig choose_rs_config(uint64_t strip_bytes, bool recovery) {
+  const uint32_t o = g_rs_override.load();
+  if (o != 0) return RsConfig{(int)(o >> 16), (int)((o >> 12) & 15u), (int)(o & 0xFFFu)};
   static const int env_vec = env_int("RAID6C_RS_VEC");
+  static const int env_unroll = env_int("RAID6C_RS_UNROLL");
   static const int env_threads = env_int("RAID6C_RS_THREADS");
-  if ((env_vec == 1 || env_vec == 2 || env_vec == 4) &&
+  if ((env_vec == 1 || env_vec == 2 || env_vec == 4) && (env_unroll == 1 || env_unroll == 4 || env_unroll == 8) &&
       (env_threads == 64 || env_threads == 128 || env_threads == 256))
-    return RsConfig{env_vec, env_threads};
+    return RsConfig{env_vec, env_unroll, env_threads};
+  // Measured on MI355X (12 data strips of 48 KiB): encode is fastest with one
+  // dword per thread and 4 strips in flight (about 80% of HBM peak); the
+  // two-data recovery multiplies by two field constants per byte and needs
+  // the wider vectors to stay near the memory rate.
+  const int vec = recovery ? 4 : 1;
+  const int cap = recovery ? 256 : 128;
   int threads = 64;
-  while (threads < 256 && (uint64_t)threads * 16 < strip_bytes) threads *= 2;
-  return RsConfig{4, threads};
+  while (threads < cap && (uint64_t)threads * vec * 4 < strip_bytes) threads *= 2;
+  return RsConfig{vec, 4, threads};
 }
 
 }  // namespace raid6c

@@ -62,3 +62,8 @@ class StripeBatch:
         """Reed-Solomon GF(256) P+Q over the same bytes (each strip a byte vector)."""
         return _lib.raid6c_rs_encode_n(self.k, self.strip_stride, self.tensor.data_ptr(), self.strip_stride,
                                        self.stripe_stride, self.nstripes, stream)
+
+    def rs_recover(self, erasures, bad_count=None, stream=None):
+        """Reed-Solomon recovery of the per-stripe erasures (device int32 (n, 2))."""
+        return _lib.raid6c_rs_recover_n(self.k, self.strip_stride, self.tensor.data_ptr(), self.strip_stride,
+                                        self.stripe_stride, self.nstripes, erasures, bad_count, stream)
