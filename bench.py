@@ -470,9 +470,10 @@ def summarize_profiles(stats_dir: str, fetch_dir: str, write_dir: str, out_dir: 
         hbm = int(round(fetch[n] * 1024 * fs + write[n] * 1024 * ws))
         lines.append(f"{n}: FETCH_SIZE {fetch[n]:.0f} KiB, WRITE_SIZE {write[n]:.0f} KiB per launch -> "
                      f"{hbm} B scaled HBM traffic; algorithmic {alg} B; ratio {hbm / alg:.5f}")
-        m = re.match(r"zp_\w+_kernel<(\d+), (\d+), (\d+)>", n)
+        m = re.match(r"zp_(\w+)_kernel<(\d+), (\d+), (\d+), (\w+)>", n)
+        split = int(m.group(5)) if m.group(1) == "split" else 1
         key = n.replace(", ", ",")
-        table[key] = {"source_sha256": digest, "config": [int(m.group(2)), int(m.group(3)), wg[n]],
+        table[key] = {"source_sha256": digest, "config": [int(m.group(3)), int(m.group(4)), wg[n], split],
                       "algorithmic_bytes": alg, "hbm_bytes_per_launch": hbm,
                       "fetch_kib": round(fetch[n]), "write_kib": round(write[n]),
                       "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
@@ -568,13 +569,16 @@ def main():
 
     dom = "recover" if rec_mean >= enc_mean else "encode"
     dom_ms = rec_mean if dom == "recover" else enc_mean
-    vec, unroll, threads = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
-    kname = f"zp_{dom}_kernel<{P},{vec},{unroll}>"
+    vec, unroll, threads, split = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
+    if split > 1:
+        kname = f"zp_split_kernel<{P},{vec},{unroll},{split}>"
+    else:
+        kname = f"zp_{dom}_kernel<{P},{vec},{unroll},false>"
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
-    traffic = lookup_traffic(kname, (vec, unroll, threads), alg_bytes)
+    traffic = lookup_traffic(kname, (vec, unroll, threads, split), alg_bytes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": kname, "launch": {"vec": vec, "unroll": unroll, "threads": threads},
+                "kernel": kname, "launch": {"vec": vec, "unroll": unroll, "threads": threads, "split": split},
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(dom_ms, 4)}
     log(f"value {value:.1f} GB/s; encode {enc_mean:.3f} ms, recovery {rec_mean:.3f} ms per launch")
 
@@ -590,11 +594,11 @@ def main():
         "encode": {"GBps_user": round(user / (enc_mean / 1e3) / 1e9, 1),
                    "hbm_frac": round(alg_bytes / (enc_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                    "ms_p50": round(pct(enc_ms, 50), 4), "ms_p99": round(pct(enc_ms, 99), 4),
-                   "launch": dict(zip(("vec", "unroll", "threads"), r.raid6c_tune_get(P, 0, W)))},
+                   "launch": dict(zip(("vec", "unroll", "threads", "split"), r.raid6c_tune_get(P, 0, W)))},
         "recover_2": {"GBps_user": round(user / (rec_mean / 1e3) / 1e9, 1),
                       "hbm_frac": round(alg_bytes / (rec_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                       "ms_p50": round(pct(rec_ms, 50), 4), "ms_p99": round(pct(rec_ms, 99), 4),
-                      "launch": dict(zip(("vec", "unroll", "threads"), r.raid6c_tune_get(P, 1, W)))},
+                      "launch": dict(zip(("vec", "unroll", "threads", "split"), r.raid6c_tune_get(P, 1, W)))},
         "roofline": roofline,
         "autotune": tuned,
     }

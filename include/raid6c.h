@@ -418,8 +418,13 @@ int raid6c_server_destroy(raid6c_server* s);
  *
  * A Z_p kernel launch is configured by `vec`, the dwords each thread moves
  * per row (1, 2 or 4), `unroll`, the number of data strips whose loads are
- * issued together (1, 2 or 4), and `threads`, the work-group size (64, 128
- * or 256).  Only some (vec, unroll) pairs are built for each prime.
+ * issued together (1, 2 or 4), `threads`, the work-group size (64, 128 or
+ * 256), and `split`: 1 = every thread of the work-group owns its own column
+ * slice; 2 or 4 = the work-group's `split` waves share one column tile of 64
+ * lanes and split the data strips between them, combining their partial
+ * sums in LDS (threads = 64*split; plain code, k <= p; an extended-parity
+ * call uses the same work-group size without the split).  Only some (vec,
+ * unroll) pairs and split factors are built for each prime.
  * The library keeps one process-wide table keyed by (p, op, row-size bucket),
  * bucket = floor(log2(row_bytes)); op 0 = encode, 1 = recovery.  Entries
  * change only speed, never results.
@@ -433,20 +438,25 @@ int raid6c_vec_mask(int p);
  * 0 when the pair is not built. */
 int raid6c_unroll_mask(int p, int vec);
 
+/* Bit mask of the split factors built for (p, vec) (bit s for split = s,
+ * s = 2, 4); 0 when none is. */
+int raid6c_split_mask(int p, int vec);
+
 /* Record the configuration for (p, op, bucket of row_bytes).
  * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, (vec, unroll) not built
- * for p, threads not 64/128/256. */
-int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads);
+ * for p, threads not 64/128/256, or split not 1 or a built factor with
+ * threads = 64*split. */
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split);
 
 /* The configuration a call with these arguments would use now.
  * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, or NULL outputs. */
-int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads);
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads, int* split);
 
 /* Forget every recorded configuration (back to the built-in rule). */
 void raid6c_tune_clear(void);
 
 /* Autotuner for the strided entry points: run every built (vec, unroll,
- * threads) configuration on the caller's stripes -- op 0: raid6c_encode_n,
+ * threads, split) configuration on the caller's stripes -- op 0: raid6c_encode_n,
  * op 1: raid6c_recover_n with `erasures` (device, as there) -- once to warm
  * up and `reps` times timed with HIP events on `stream`, then record the
  * fastest for (p, op, row-size bucket) and return its mean time per launch

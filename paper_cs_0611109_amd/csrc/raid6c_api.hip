@@ -152,7 +152,10 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_UNSUPPORTED, "p = %d is not built", p);
   const ZpConfig cfg = choose_config(*e, kind, a.row_bytes);
-  const uint64_t tile_bytes = (uint64_t)cfg.threads * cfg.vec * 4;
+  // A split-K work-group covers 64 lanes x vec dwords of a row (plain code);
+  // otherwise every thread its own vec dwords.
+  const bool split = cfg.split > 1 && a.k <= p;
+  const uint64_t tile_bytes = (uint64_t)(split ? 64 : cfg.threads) * cfg.vec * 4;
   a.tiles = (uint32_t)((a.row_bytes + tile_bytes - 1) / tile_bytes);
   // Keep grid * threads below 2^31.
   const uint64_t max_blocks = (((uint64_t)1 << 31) / cfg.threads);
@@ -161,6 +164,7 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
   while (done < nstripes) {
     const size_t n = (nstripes - done) < chunk ? (nstripes - done) : chunk;
     ZpArgs b = a;
+    b.kind = kind;
     if (done != 0) {
       for (int j = 0; j < a.k + 2; ++j) b.strip[j] = a.strip[j] + done * a.stripe_stride;
       if (a.erasures != nullptr) b.erasures = a.erasures + 2 * done;
@@ -424,7 +428,7 @@ int raid6c_unroll_mask(int p, int vec) {
   return e->unroll_mask[vec];
 }
 
-int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads) {
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split) {
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
@@ -433,22 +437,33 @@ int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int th
     return fail(RAID6C_E_ARG, "(vec = %d, unroll = %d) is not built for p = %d", vec, unroll, p);
   if (!(threads == 64 || threads == 128 || threads == 256))
     return fail(RAID6C_E_ARG, "threads = %d must be 64, 128 or 256", threads);
+  if (!e->has(ZpConfig{vec, unroll, threads, split}))
+    return fail(RAID6C_E_ARG, "split = %d is not built for p = %d, vec = %d with threads = %d", split, p, vec,
+                threads);
   if (row_bytes == 0) return fail(RAID6C_E_ARG, "row_bytes must be positive");
-  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads});
+  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads, split});
   return RAID6C_OK;
 }
 
-int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads) {
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads, int* split) {
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
   if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
-  if (vec == nullptr || unroll == nullptr || threads == nullptr) return fail(RAID6C_E_ARG, "NULL output");
+  if (vec == nullptr || unroll == nullptr || threads == nullptr || split == nullptr)
+    return fail(RAID6C_E_ARG, "NULL output");
   const ZpConfig c = choose_config(*e, (ZpKind)op, row_bytes);
   *vec = c.vec;
   *unroll = c.unroll;
   *threads = c.threads;
+  *split = c.split;
   return RAID6C_OK;
+}
+
+int raid6c_split_mask(int p, int vec) {
+  const ZpPrimeEntry* e = zp_prime_entry(p);
+  if (e == nullptr || !(vec == 1 || vec == 2 || vec == 4)) return 0;
+  return e->split_mask[vec];
 }
 
 void raid6c_tune_clear(void) { clear_tuned(); }
@@ -479,30 +494,39 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
   const int bucket = row_bucket(row_bytes);
   ZpArgs a = strided_args(k, row_bytes, base, strip_stride, stripe_stride);
   a.erasures = op == 1 ? erasures : nullptr;
-  ZpConfig best{0, 0, 0};
+  ZpConfig best{0, 0, 0, 1};
   float best_t = 1e30f;
-  for (int vec = 1; vec <= 4 && rc == RAID6C_OK; vec *= 2) {
-    for (int unroll = 1; unroll <= 4 && rc == RAID6C_OK; unroll *= 2) {
+  // Every built configuration: (vec, unroll) with a work-group of 64, 128 or
+  // 256 threads on separate column tiles, and split-K with 2 or 4 waves on
+  // one tile (plain code only).
+  ZpConfig cands[9 * 5];
+  int ncand = 0;
+  for (int vec = 1; vec <= 4; vec *= 2)
+    for (int unroll = 1; unroll <= 4; unroll *= 2) {
       if (!e->has(vec, unroll)) continue;
-      for (int threads = 64; threads <= 256 && rc == RAID6C_OK; threads *= 2) {
-        set_tuned(p, kind, bucket, ZpConfig{vec, unroll, threads});
-        if ((rc = launch_zp(p, kind, a, nstripes, stream)) != RAID6C_OK) break;
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < reps && rc == RAID6C_OK; ++r) rc = launch_zp(p, kind, a, nstripes, stream);
-        (void)hipEventRecord(e1, s);
-        if (rc != RAID6C_OK) break;
-        if (hipEventSynchronize(e1) != hipSuccess) {
-          rc = fail(RAID6C_E_HIP, "hipEventSynchronize failed");
-          break;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= (float)reps;
-        if (ms < best_t) {
-          best_t = ms;
-          best = ZpConfig{vec, unroll, threads};
-        }
-      }
+      for (int threads = 64; threads <= 256; threads *= 2) cands[ncand++] = ZpConfig{vec, unroll, threads, 1};
+      if (k <= p)
+        for (int sp = 2; sp <= 4; sp *= 2)
+          if (e->split_mask[vec] & sp) cands[ncand++] = ZpConfig{vec, unroll, 64 * sp, sp};
+    }
+  for (int ci = 0; ci < ncand && rc == RAID6C_OK; ++ci) {
+    const ZpConfig cfg = cands[ci];
+    set_tuned(p, kind, bucket, cfg);
+    if ((rc = launch_zp(p, kind, a, nstripes, stream)) != RAID6C_OK) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && rc == RAID6C_OK; ++r) rc = launch_zp(p, kind, a, nstripes, stream);
+    (void)hipEventRecord(e1, s);
+    if (rc != RAID6C_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(RAID6C_E_HIP, "hipEventSynchronize failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (ms < best_t) {
+      best_t = ms;
+      best = cfg;
     }
   }
   (void)hipEventDestroy(e0);

@@ -68,32 +68,40 @@ struct ZpArgs {
                                // src_base + s*src_stripe_stride + j*src_strip_stride
   uint64_t src_strip_stride;   // and copied to strip j; NULL = encode in place
   uint64_t src_stripe_stride;
+  int32_t kind;                // ZpKind of the launch (set by the launcher)
 };
 
 // Launch configuration of a Z_p kernel.
 struct ZpConfig {
-  int vec;      // dwords per thread and row: 1, 2 or 4
-  int unroll;   // data strips whose loads are issued together: 1, 2 or 4
-  int threads;  // work-group size: 64, 128 or 256
+  int vec;        // dwords per thread and row: 1, 2 or 4
+  int unroll;     // data strips whose loads are issued together: 1, 2 or 4
+  int threads;    // work-group size: 64, 128 or 256
+  int split = 1;  // waves sharing one column tile (1, 2, 4); threads = 64*split when > 1
 };
 
 enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
 
-// Per-prime launchers, two translation units per prime (zp_kernels.hip).
+// Per-prime launchers, three translation units per prime (zp_kernels.hip).
 // Return hipSuccess or the launch error (hipErrorInvalidValue for a
 // configuration that is not built).
 typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a,
                                  uint32_t grid, hipStream_t stream);
 struct ZpPrimeEntry {
   int p;
-  ZpLauncher launch;       // plain code, k <= p
+  ZpLauncher launch;       // plain code, k <= p (split-K configurations included)
   ZpLauncher launch_ext;   // extended Q parity, p < k <= 2p-1
   int vec_mask;        // bit v set when vec = v is instantiated (bits 1, 2, 4)
   int unroll_mask[5];  // per vec: bit u set when (vec, unroll = u) is instantiated
+  int split_mask[5];   // per vec: bit s set when split = s (2, 4) is built (plain code)
 
   bool has(int vec, int unroll) const {
     return (vec == 1 || vec == 2 || vec == 4) && (vec_mask & vec) &&
            (unroll == 1 || unroll == 2 || unroll == 4) && (unroll_mask[vec] & unroll);
+  }
+  bool has(const ZpConfig& c) const {
+    if (!has(c.vec, c.unroll)) return false;
+    if (c.split == 1) return c.threads == 64 || c.threads == 128 || c.threads == 256;
+    return (c.split == 2 || c.split == 4) && (split_mask[c.vec] & c.split) && c.threads == 64 * c.split;
   }
 };
 

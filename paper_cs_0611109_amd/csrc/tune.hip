@@ -10,7 +10,8 @@ namespace raid6c {
 namespace {
 
 constexpr int kBuckets = 31;
-// Packed (vec << 16 | unroll << 12 | threads), 0 = no entry; [p][kind][bucket].
+// Packed (split << 20 | vec << 16 | unroll << 12 | threads), 0 = no entry;
+// [p][kind][bucket].
 std::atomic<uint32_t> g_table[kMaxPrime + 1][2][kBuckets];
 
 int env_int(const char* name) {
@@ -18,16 +19,14 @@ int env_int(const char* name) {
   return s ? atoi(s) : 0;
 }
 
-bool valid(const ZpPrimeEntry& e, const ZpConfig& c) {
-  return e.has(c.vec, c.unroll) && (c.threads == 64 || c.threads == 128 || c.threads == 256);
-}
+bool valid(const ZpPrimeEntry& e, const ZpConfig& c) { return e.has(c); }
 
 uint32_t pack(const ZpConfig& c) {
-  return ((uint32_t)c.vec << 16) | ((uint32_t)c.unroll << 12) | (uint32_t)c.threads;
+  return ((uint32_t)c.split << 20) | ((uint32_t)c.vec << 16) | ((uint32_t)c.unroll << 12) | (uint32_t)c.threads;
 }
 
 ZpConfig unpack(uint32_t t) {
-  return ZpConfig{(int)(t >> 16), (int)((t >> 12) & 0xF), (int)(t & 0xFFF)};
+  return ZpConfig{(int)((t >> 16) & 0xF), (int)((t >> 12) & 0xF), (int)(t & 0xFFF), (int)((t >> 20) & 0xF)};
 }
 
 }  // namespace
@@ -57,7 +56,7 @@ ZpConfig default_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) 
   // unroll*(p-1)*vec loads + ~24 for addresses and temporaries; a SIMD holds
   // floor(512 / registers) waves, at most 8.
   const int p = e.p;
-  ZpConfig best{0, 0, 64};
+  ZpConfig best{0, 0, 64, 1};
   long best_score = -1;
   for (int vec = 1; vec <= 4; vec *= 2) {
     for (int unroll = 1; unroll <= 4; unroll *= 2) {
@@ -71,9 +70,16 @@ ZpConfig default_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) 
       const long score = (long)(waves * unroll * (p - 1) * vec * used * 1000.0);
       if (score > best_score) {
         best_score = score;
-        best = ZpConfig{vec, unroll, 64};
+        best = ZpConfig{vec, unroll, 64, 1};
       }
     }
+  }
+  // Several waves per column tile (split-K) with two dwords per lane, where
+  // their partials fit in LDS: fewer stripes in flight at once, which
+  // measured fastest on MI355X for the primes that allow it (p <= 29).
+  if (row_bytes >= 64 * 2 * 4) {
+    if (e.split_mask[2] & 4) return ZpConfig{2, 1, 256, 4};
+    if (e.split_mask[2] & 2) return ZpConfig{2, 1, 128, 2};
   }
   return best;
 }
@@ -83,8 +89,9 @@ ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) {
   static const int env_vec = env_int("RAID6C_ZP_VEC");
   static const int env_unroll = env_int("RAID6C_ZP_UNROLL");
   static const int env_threads = env_int("RAID6C_ZP_THREADS");
+  static const int env_split = env_int("RAID6C_ZP_SPLIT");
   if (env_vec != 0 && env_threads != 0) {
-    const ZpConfig c{env_vec, env_unroll ? env_unroll : 1, env_threads};
+    const ZpConfig c{env_vec, env_unroll ? env_unroll : 1, env_threads, env_split ? env_split : 1};
     if (valid(e, c)) return c;
   }
   const uint32_t t = g_table[e.p][kind][row_bucket(row_bytes)].load();

@@ -432,10 +432,16 @@ __device__ __forceinline__ uint64_t inverse_mod_phi(uint64_t f, int p) {
   return s1;
 }
 
-// Recovery of one tile.  `lds` points at this thread's column of a region of
-// P rows of one dword, row stride `ls` dwords; only this thread touches it.
-// The data-dependent row permutations are done one dword column at a time,
-// so the region does not grow with the vector width.
+// Finishing of a recovery from the syndromes of the surviving strips, for
+// the cases D, DQ, DP and DD (a thread's V-dword column slice):
+//   D, DQ, DD: ap = P + sum of the surviving data strips (dP);
+//   DP:        ap = sum of the surviving data strips (P is rebuilt);
+//   DP, DD:    aq = Q~ + sum of the surviving g_t D_t, in C (dQ~);
+//   DQ:        aq = sum of the surviving g_t D_t, in C (Q is rebuilt).
+// `lds` points at this thread's column of a region of P rows of one dword,
+// row stride `ls` dwords; only this thread touches it.  The data-dependent
+// row permutations are done one dword column at a time, so the region does
+// not grow with the vector width.
 //
 // EXT: the stripe has k > p data strips and the extended Q parity of
 // Section 3.3 (coefficient g_t = x^t for t < p, 1 + x^{t-p+1} for t >= p).
@@ -449,63 +455,26 @@ __device__ __forceinline__ uint64_t inverse_mod_phi(uint64_t f, int p) {
 // it is the trinomial 1 + x^x + x^j, whose inverse h (Theorem 3.3.3 makes it
 // exist) is computed per wave and applied as the cyclic convolution
 // D~[u] = sum_{i in h} G~[u - i] in C.
-template <int P, int V, int U, bool EXT, class C>
-__device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_in, uint32_t* lds, int ls) {
+template <int P, int V, bool EXT, class C>
+__device__ __forceinline__ void finish_recover(const C& c, int k, const Case& cs,
+                                               typename vec_t<V>::type (&ap)[P - 1],
+                                               typename vec_t<V>::type (&aq)[P], uint32_t* lds, int ls) {
   typedef typename vec_t<V>::type VT;
   typedef comp<V> CP;
   constexpr int R = P - 1;
   const int iP = k, iQ = k + 1;
-  // The case is uniform over the wave; keep it (and every strip address
-  // derived from it) in scalar registers.
-  const Case cs{__builtin_amdgcn_readfirstlane(cs_in.op), __builtin_amdgcn_readfirstlane(cs_in.x),
-                __builtin_amdgcn_readfirstlane(cs_in.y)};
-
-  switch (cs.op) {
-    case OP_PQ:
-      tile_encode<P, V, U, EXT>(c, k, true, true);
-      return;
-    case OP_P:
-      tile_encode<P, V, U, EXT>(c, k, true, false);
-      return;
-    case OP_Q:
-      tile_encode<P, V, U, EXT>(c, k, false, true);
-      return;
-    default:
-      break;
-  }
-
-  VT ap[R], aq[P];
-#pragma unroll
-  for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
 
   if (cs.op == OP_D) {
     // D_x = P + sum_{t != x} D_t.
-    load_into<P, V>(c, iP, ap);
-    stream_range<P, V, U, true, false>(c, k - 1, 0, cs.x, -1, ap, aq);
     store_strip<P, V>(c, cs.x, ap);
     return;
   }
-
-  // dP (with P itself, as the recovery needs it) in ap, dQ~ (without Q) in
-  // aq.  With extended parity acc_p must start at zero, so P comes last.
-  auto syndromes = [&](int x, int y) {
-    if constexpr (EXT) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
-      stream_data<P, V, U, true, true, true>(c, k, x, y, ap, aq);
-      xor_from<P, V>(c, iP, ap);
-    } else {
-      load_into<P, V>(c, iP, ap);
-      stream_data<P, V, U, true, true, false>(c, k, x, y, ap, aq);
-    }
-  };
 
   if (cs.op == OP_DQ) {
     // D_x = dP;  Q = sum_{t != x} g_t D_t + g_x D_x.
     const int x = cs.x;
     const bool xe = EXT && x >= P;        // g_x = 1 + x^{sh}, else x^{sh}
     const int sh = xe ? x - P + 1 : x;
-    syndromes(x, -1);
 #pragma unroll
     for (int cc = 0; cc < V; ++cc) {
 #pragma unroll
@@ -531,10 +500,6 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
   if (cs.op == OP_DP) {
     // g_x D_x = Q + sum_{t != x} g_t D_t;  P = sum_{t != x} D_t + D_x.
     const int x = cs.x;
-#pragma unroll
-    for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
-    stream_data<P, V, U, true, true, EXT>(c, k, x, -1, ap, aq);
-    xor_from<P, V>(c, iQ, aq);
     if (EXT && x >= P) {
       // (1 + x^j) D_x = dQ, j = x-p+1: the chain on the lift dQ~.
       const int j = x - P + 1;
@@ -586,8 +551,6 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
 
   // OP_DD: data x < y.
   const int x = cs.x, y = cs.y;
-  syndromes(x, y);
-  xor_from<P, V>(c, iQ, aq);
 
   if (EXT && x < P && y >= P) {
     // (1 + x^x + x^j) D_y = x^x dP + dQ =: G, j = y-p+1.  (x = 0 gives x^j,
@@ -662,6 +625,71 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
   for (int r = 0; r < R; ++r) {
     st<VT>(by, r, W, c.col, aq[r]);
     st<VT>(bx, r, W, c.col, aq[r] ^ ap[r]);
+  }
+}
+
+// Recovery of one tile by one thread's V-dword column slice: the streaming
+// phase for the case, then finish_recover.  `lds`, `ls` as there.
+template <int P, int V, int U, bool EXT, class C>
+__device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_in, uint32_t* lds, int ls) {
+  typedef typename vec_t<V>::type VT;
+  constexpr int R = P - 1;
+  const int iP = k, iQ = k + 1;
+  // The case is uniform over the wave; keep it (and every strip address
+  // derived from it) in scalar registers.
+  const Case cs{__builtin_amdgcn_readfirstlane(cs_in.op), __builtin_amdgcn_readfirstlane(cs_in.x),
+                __builtin_amdgcn_readfirstlane(cs_in.y)};
+
+  switch (cs.op) {
+    case OP_PQ:
+      tile_encode<P, V, U, EXT>(c, k, true, true);
+      return;
+    case OP_P:
+      tile_encode<P, V, U, EXT>(c, k, true, false);
+      return;
+    case OP_Q:
+      tile_encode<P, V, U, EXT>(c, k, false, true);
+      return;
+    default:
+      break;
+  }
+
+  VT ap[R], aq[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
+
+  // dP with P itself in ap (cases D, DQ, DD).  With extended parity acc_p
+  // must start at zero, so P comes last there.
+  auto with_p = [&](int y) {
+    if constexpr (EXT) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
+      stream_data<P, V, U, true, true, true>(c, k, cs.x, y, ap, aq);
+      xor_from<P, V>(c, iP, ap);
+    } else {
+      load_into<P, V>(c, iP, ap);
+      stream_data<P, V, U, true, true, false>(c, k, cs.x, y, ap, aq);
+    }
+  };
+  // Each case keeps its own streaming code and finishing, so that the
+  // compiler allocates registers per case.
+  if (cs.op == OP_D) {
+    load_into<P, V>(c, iP, ap);
+    stream_range<P, V, U, true, false>(c, k - 1, 0, cs.x, -1, ap, aq);
+    finish_recover<P, V, EXT>(c, k, Case{OP_D, cs.x, -1}, ap, aq, lds, ls);
+  } else if (cs.op == OP_DP) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
+    stream_data<P, V, U, true, true, EXT>(c, k, cs.x, -1, ap, aq);
+    xor_from<P, V>(c, iQ, aq);
+    finish_recover<P, V, EXT>(c, k, Case{OP_DP, cs.x, -1}, ap, aq, lds, ls);
+  } else if (cs.op == OP_DQ) {
+    with_p(-1);
+    finish_recover<P, V, EXT>(c, k, Case{OP_DQ, cs.x, -1}, ap, aq, lds, ls);
+  } else {
+    with_p(cs.y);
+    xor_from<P, V>(c, iQ, aq);
+    finish_recover<P, V, EXT>(c, k, Case{OP_DD, cs.x, cs.y}, ap, aq, lds, ls);
   }
 }
 

@@ -1,19 +1,24 @@
 // zp_kernels.hip -- Z_p-RAID encode and recovery kernels for one prime.
 //
-// This file is compiled twice per supported prime, with -DRAID6C_P=<p> and
-// -DRAID6C_EXT=0 or 1: the plain code (k <= p) and the extended Q parity
-// (p < k <= 2p-1, Section 3.3) go to separate objects, so that the code of
-// one never shapes the compiler's choices for the other.  Each pair of
-// objects contributes one entry to the dispatch table of the host API.
+// This file is compiled three times per supported prime, with
+// -DRAID6C_P=<p> and -DRAID6C_VARIANT=
+//   0  the plain code (k <= p), one column slice per thread;
+//   1  the extended Q parity (p < k <= 2p-1, Section 3.3), same mapping;
+//   2  the plain code split-K: the waves of a work-group share a column tile
+//      and split the data strips.
+// Each object is compiled alone so that the code of one never shapes the
+// compiler's choices for the others; object 0 holds the dispatch entry and
+// calls into the other two.
 //
-// Grid: one work-group per (stripe, column tile); a tile is `threads` threads
-// times V dwords of every row.  Work-group i handles stripe i / tiles and tile
-// i % tiles, so the stripe and its erasure case are uniform over the group and
-// all strip addresses live in scalar registers.
-#ifndef RAID6C_EXT
-#define RAID6C_EXT 0
+// Grid (variants 0, 1): one work-group per (stripe, column tile); a tile is
+// `threads` threads times V dwords of every row.  Work-group i handles stripe
+// i / tiles and tile i % tiles, so the stripe and its erasure case are uniform
+// over the group and all strip addresses live in scalar registers.  Variant
+// 2: the same with a tile of 64 lanes times V dwords.
+#ifndef RAID6C_VARIANT
+#define RAID6C_VARIANT 0
 #endif
-#define RAID6C_UNIFORM_ROW_HINT RAID6C_EXT
+#define RAID6C_UNIFORM_ROW_HINT (RAID6C_VARIANT != 0)
 #include "zp_core.hpp"
 
 #ifndef RAID6C_P
@@ -28,7 +33,8 @@ namespace raid6c {
 namespace {
 
 constexpr int kP = RAID6C_P;
-constexpr bool kExt = RAID6C_EXT != 0;
+constexpr bool kExt = RAID6C_VARIANT == 1;
+constexpr int sk_lds_bytes_any(int V, int S) { return S * (2 * kP - 1) * 64 * V * 4; }
 static_assert(kP >= 3 && kP <= kMaxPrime && (kP % 2) == 1, "unsupported prime");
 
 // Vector widths built for this prime: wider vectors need (2p-1)*V registers
@@ -71,11 +77,145 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   tile_recover<P, V, U, EXT>(c, a.k, cs, lds, (int)blockDim.x);
 }
 
+#if RAID6C_VARIANT == 2
+// Split-K (plain code only).  The S waves of a work-group share one column
+// tile of 64 lanes x V dwords and split the data strips into S contiguous
+// ranges [t0, t1); each wave runs the streaming phase on its range.  Its Q
+// partial is x^{t0} times what Horner leaves (sum_t x^{t-t0} D_t), so it
+// goes to LDS rotated by t0, next to the P partial; wave 0 (whose range starts
+// at t = 0) also adds P and/or Q where the case needs them.  After a barrier:
+//  * encode-like cases: the waves split the rows, sum the S partials and
+//    store P and the reduced Q (row r plus row p-1) V dwords per lane;
+//  * recoveries: one thread per dword column sums its column of the
+//    partials and runs the common finishing (finish_recover) on it, with its
+//    LDS column as the permutation scratch.
+// Many waves on one stripe at a time keeps fewer stripes in flight, which
+// the memory system rewards.
+template <int P, int V, int U, int S>
+__global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
+  typedef typename vec_t<V>::type VT;
+  typedef comp<V> CP;
+  constexpr int R = P - 1;
+  constexpr int NR = 2 * P - 1;
+  constexpr int CS = 64 * V;                  // dword columns of the tile
+  extern __shared__ __align__(16) uint32_t part[];   // [S][NR][CS]
+  const uint32_t stripe = blockIdx.x / a.tiles;
+  const uint32_t tile = blockIdx.x - stripe * a.tiles;
+  Case cs{OP_PQ, -1, -1};            // an encode writes P and Q
+  if (a.kind == KIND_RECOVER) {
+    // Per-stripe entries, or the uniform pair of a single-stripe call.
+    int e0 = a.e0, e1 = a.e1;
+    if (a.erasures != nullptr) {
+      e0 = __builtin_amdgcn_readfirstlane(a.erasures[2 * (uint64_t)stripe]);
+      e1 = __builtin_amdgcn_readfirstlane(a.erasures[2 * (uint64_t)stripe + 1]);
+    }
+    cs = classify(a.k, e0, e1);
+    if (cs.op == OP_BAD) {   // uniform over the work-group: no barrier is skipped
+      if (tile == 0 && threadIdx.x == 0 && a.bad_count != nullptr) atomicAdd(a.bad_count, 1);
+      return;
+    }
+  }
+  cs = Case{__builtin_amdgcn_readfirstlane(cs.op), __builtin_amdgcn_readfirstlane(cs.x),
+            __builtin_amdgcn_readfirstlane(cs.y)};
+  const int k = a.k;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const uint32_t col = (tile * 64 + lane) * (V * 4);
+  const bool live = col < a.row_bytes;
+  const uint32_t strip_bytes = (uint32_t)((P - 1) * a.row_bytes);
+  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
+                    strip_bytes};
+  const int per = (k + S - 1) / S;
+  const int t0 = w * per;
+  const int t1 = t0 + per < k ? t0 + per : k;
+  // Erased data strips are skipped; P/Q are rebuilt, never read, in their cases.
+  const int x = (cs.op == OP_D || cs.op == OP_DP || cs.op == OP_DQ || cs.op == OP_DD) ? cs.x : -1;
+  const int y = cs.op == OP_DD ? cs.y : -1;
+  VT ap[R], aq[P];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
+#pragma unroll
+  for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
+  if (live) {
+    if (t0 < t1) stream_range<P, V, U, true, true>(c, t1 - 1, t0, x, y, ap, aq);
+    if (w == 0) {
+      if (cs.op == OP_D || cs.op == OP_DQ || cs.op == OP_DD) xor_from<P, V>(c, k, ap);
+      if (cs.op == OP_DP || cs.op == OP_DD) xor_from<P, V>(c, k + 1, aq);
+    }
+  }
+  uint32_t* my = part + (size_t)w * NR * CS + lane * V;
+  const int rot = t0 % P;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < V; ++j) my[r * CS + j] = CP::get(ap[r], j);
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    int d = u + rot;
+    if (d >= P) d -= P;
+#pragma unroll
+    for (int j = 0; j < V; ++j) my[(R + d) * CS + j] = CP::get(aq[u], j);
+  }
+  __syncthreads();
+
+  if (cs.op == OP_PQ || cs.op == OP_P || cs.op == OP_Q) {
+    if (!live) return;
+    auto row = [&](int rr) {
+      VT v = (VT)(0u);
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          CP::set(v, j, CP::get(v, j) ^ part[((size_t)s2 * NR + rr) * CS + lane * V + j]);
+      return v;
+    };
+    const VT top = row(R + R);
+    const __amdgpu_buffer_rsrc_t bp = c.strip(k), bq = c.strip(k + 1);
+    const uint64_t W = c.W();
+    for (int r = w; r < R; r += S) {
+      if (cs.op != OP_Q) st<VT>(bp, r, W, col, row(r));
+      if (cs.op != OP_P) st<VT>(bq, r, W, col, row(R + r) ^ top);
+    }
+    return;
+  }
+
+  for (int cc = threadIdx.x; cc < CS; cc += 64 * S) {
+    const uint32_t cb = tile * (uint32_t)(CS * 4) + (uint32_t)cc * 4u;
+    if (cb >= a.row_bytes) break;
+    uint32_t fp[R], fq[P];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uint32_t v = 0u;
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) v ^= part[((size_t)s2 * NR + r) * CS + cc];
+      fp[r] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      uint32_t v = 0u;
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) v ^= part[((size_t)s2 * NR + R + u) * CS + cc];
+      fq[u] = v;
+    }
+    // Only this thread uses column cc of the partials from here on.
+    const ColsTable cd{&a, (uint64_t)stripe * a.stripe_stride, 0, cb, strip_bytes};
+    finish_recover<P, 1, false>(cd, k, cs, fp, fq, part + cc, CS);
+  }
+}
+#endif
+
 // (vec, unroll) pairs built for this prime: accumulators take (2p-1)*vec
 // dwords per thread and a batch of loads unroll*(p-1)*vec more.
 template <int V, int U>
 constexpr bool built() {
   return (kVecMask & V) != 0 && (2 * kP - 1) * V + U * (kP - 1) * V <= 192;
+}
+
+// Split factors S (2, 4) built with vector width V: the partials of S
+// waves fit in 64 KiB of LDS.
+constexpr int split_mask(int v) {
+  return !(kVecMask & v) ? 0
+                         : ((sk_lds_bytes_any(v, 2) <= 65536 ? 2 : 0) | (sk_lds_bytes_any(v, 4) <= 65536 ? 4 : 0));
 }
 
 constexpr int unroll_mask(int v) {
@@ -89,19 +229,38 @@ template <int V, int U>
 hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                      hipStream_t stream) {
   if constexpr (built<V, U>()) {
+#if RAID6C_VARIANT == 2
+    (void)kind;
+    if (a.k > kP) return hipErrorInvalidValue;
+    const dim3 g(grid);
+    if constexpr ((split_mask(V) & 2) != 0) {
+      if (cfg.split == 2) {
+        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 2>), g, dim3(128), sk_lds_bytes_any(V, 2), stream, a);
+        return hipGetLastError();
+      }
+    }
+    if constexpr ((split_mask(V) & 4) != 0) {
+      if (cfg.split == 4) {
+        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 4>), g, dim3(256), sk_lds_bytes_any(V, 4), stream, a);
+        return hipGetLastError();
+      }
+    }
+    return hipErrorInvalidValue;
+#else
+    if ((a.k > kP) != kExt) return hipErrorInvalidValue;
     const dim3 g(grid), b(cfg.threads);
     const size_t lds = (size_t)kP * cfg.threads * 4;
-    if ((a.k > kP) != kExt) return hipErrorInvalidValue;
     if (kind == KIND_ENCODE) hipLaunchKernelGGL((zp_encode_kernel<kP, V, U, kExt>), g, b, 0, stream, a);
     else hipLaunchKernelGGL((zp_recover_kernel<kP, V, U, kExt>), g, b, lds, stream, a);
     return hipGetLastError();
+#endif
   } else {
     return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
-                  hipStream_t stream) {
+hipError_t launch_here(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                       hipStream_t stream) {
   switch (cfg.vec * 8 + cfg.unroll) {
     case 9: return launch_vu<1, 1>(kind, cfg, a, grid, stream);
     case 10: return launch_vu<1, 2>(kind, cfg, a, grid, stream);
@@ -118,18 +277,35 @@ hipError_t launch(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t gr
 
 }  // namespace
 
-#if RAID6C_EXT
-hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
-                                                hipStream_t stream) {
-  return launch(kind, cfg, a, grid, stream);
-}
-#else
+// Launchers of the other two objects of this prime.
 hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                                                 hipStream_t stream);
+hipError_t RAID6C_CAT(zp_launch_split_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                                                  hipStream_t stream);
+
+#if RAID6C_VARIANT == 1
+hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                                                hipStream_t stream) {
+  return launch_here(kind, cfg, a, grid, stream);
+}
+#elif RAID6C_VARIANT == 2
+hipError_t RAID6C_CAT(zp_launch_split_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                                                  hipStream_t stream) {
+  return launch_here(kind, cfg, a, grid, stream);
+}
+#else
+namespace {
+// Plain code: split-K configurations go to the split object.
+hipError_t launch_plain(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid, hipStream_t stream) {
+  if (cfg.split > 1) return RAID6C_CAT(zp_launch_split_, RAID6C_P)(kind, cfg, a, grid, stream);
+  return launch_here(kind, cfg, a, grid, stream);
+}
+}  // namespace
 
 const ZpPrimeEntry* RAID6C_CAT(zp_entry_, RAID6C_P)() {
-  static const ZpPrimeEntry e{kP, &launch, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
-                              {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)}};
+  static const ZpPrimeEntry e{kP, &launch_plain, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
+                              {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)},
+                              {0, split_mask(1), split_mask(2), 0, split_mask(4)}};
   return &e;
 }
 #endif

@@ -131,11 +131,13 @@ def test_rs_argument_checks():
 def test_tuning_table():
     r.raid6c_tune_clear()
     d0 = r.raid6c_tune_get(13, 0, 4096)
-    assert d0[0] in (1, 2, 4) and d0[1] in (1, 2, 4) and d0[2] in (64, 128, 256)
+    assert d0[0] in (1, 2, 4) and d0[1] in (1, 2, 4) and d0[2] in (64, 128, 256) and d0[3] in (1, 2, 4)
     r.raid6c_tune_set(13, 0, 4096, 1, 2, 128)
-    assert r.raid6c_tune_get(13, 0, 4096) == (1, 2, 128)
-    assert r.raid6c_tune_get(13, 0, 4096 + 2048) == (1, 2, 128)     # same power-of-two bucket
-    assert r.raid6c_tune_get(13, 0, 8192) == d0 or r.raid6c_tune_get(13, 0, 8192) != (1, 2, 128)
+    assert r.raid6c_tune_get(13, 0, 4096) == (1, 2, 128, 1)
+    assert r.raid6c_tune_get(13, 0, 4096 + 2048) == (1, 2, 128, 1)     # same power-of-two bucket
+    assert r.raid6c_tune_get(13, 0, 8192) == d0 or r.raid6c_tune_get(13, 0, 8192) != (1, 2, 128, 1)
+    r.raid6c_tune_set(13, 1, 4096, 2, 1, 256, 4)
+    assert r.raid6c_tune_get(13, 1, 4096) == (2, 1, 256, 4)
     r.raid6c_tune_clear()
     assert r.raid6c_tune_get(13, 0, 4096) == d0
     _err(r.raid6c_tune_set, 9, 0, 64, 1, 1, 64)
@@ -144,20 +146,28 @@ def test_tuning_table():
     _err(r.raid6c_tune_set, 13, 2, 64, 1, 1, 64)
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 1, 96)
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 3, 64)
+    _err(r.raid6c_tune_set, 13, 0, 64, 2, 1, 128, 4)   # split 4 needs 256 threads
+    _err(r.raid6c_tune_set, 13, 0, 64, 2, 1, 256, 3)   # no split 3
+    _err(r.raid6c_tune_set, 61, 0, 64, 1, 1, 256, 4)   # partials of 4 waves exceed 64 KiB of LDS at p = 61
 
 
 def test_built_configurations():
     for p in range(3, r.raid6c_max_prime() + 1):
         if not r.raid6c_is_supported_prime(p):
             assert r.raid6c_unroll_mask(p, 1) == 0
+            assert r.raid6c_split_mask(p, 1) == 0
             continue
         assert r.raid6c_unroll_mask(p, 1) & 1            # (vec 1, unroll 1) always built
         for v in (1, 2, 4):
             m = r.raid6c_unroll_mask(p, v)
             assert (m != 0) <= bool(r.raid6c_vec_mask(p) & v)
-        v, u, t = r.raid6c_tune_get(p, 1, 1024)
+            # split s is built exactly when s waves' partials (2p-1 rows of 64*v dwords) fit in 64 KiB
+            for sp in (2, 4):
+                fits = sp * (2 * p - 1) * 64 * v * 4 <= 65536
+                assert bool(r.raid6c_split_mask(p, v) & sp) == (fits and m != 0), (p, v, sp)
+        v, u, t, sp = r.raid6c_tune_get(p, 1, 1024)
         assert r.raid6c_unroll_mask(p, v) & u
-
+        assert sp == 1 or (r.raid6c_split_mask(p, v) & sp and t == 64 * sp)
 
 def test_plan_rejects_bad_jobs_before_device_work():
     J = r.raid6c_job

@@ -123,12 +123,15 @@ def test_extended_every_launch_configuration(p):
         for u in (1, 2, 4):
             if not r.raid6c_unroll_mask(p, v) & u:
                 continue
-            for t in (64, 128, 256):
-                log(f"extended config p={p} k={k} vec={v} unroll={u} threads={t}")
-                r.raid6c_tune_set(p, 0, w, v, u, t)
-                r.raid6c_tune_set(p, 1, w, v, u, t)
-                assert np.array_equal(_encode(want[:2], p, k, w), want[:2]), (v, u, t)
-                assert np.array_equal(_recover(want, p, k, w, er), want), (v, u, t)
+            # split-K entries apply to the plain code; an extended stripe runs
+            # them as plain work-groups of the same size
+            cfgs = [(t, 1) for t in (64, 128, 256)] + [(64 * sp, sp) for sp in (2, 4) if r.raid6c_split_mask(p, v) & sp]
+            for t, sp in cfgs:
+                log(f"extended config p={p} k={k} vec={v} unroll={u} threads={t} split={sp}")
+                r.raid6c_tune_set(p, 0, w, v, u, t, sp)
+                r.raid6c_tune_set(p, 1, w, v, u, t, sp)
+                assert np.array_equal(_encode(want[:2], p, k, w), want[:2]), (v, u, t, sp)
+                assert np.array_equal(_recover(want, p, k, w, er), want), (v, u, t, sp)
     r.raid6c_tune_clear()
 
 

@@ -51,8 +51,15 @@ def _recover_on_gpu(want, p, k, w, er):
 
 
 def _configs(p):
-    return [(v, u, t) for v in (1, 2, 4) for u in (1, 2, 4) if r.raid6c_unroll_mask(p, v) & u
-            for t in (64, 128, 256)]
+    """Every built launch configuration (vec, unroll, threads, split)."""
+    out = []
+    for v in (1, 2, 4):
+        for u in (1, 2, 4):
+            if not r.raid6c_unroll_mask(p, v) & u:
+                continue
+            out += [(v, u, t, 1) for t in (64, 128, 256)]
+            out += [(v, u, 64 * sp, sp) for sp in (2, 4) if r.raid6c_split_mask(p, v) & sp]
+    return out
 
 
 @pytest.fixture(autouse=True)
@@ -94,15 +101,41 @@ def test_recover_every_case_matches_oracle(p):
 @pytest.mark.parametrize("p", [3, 5, 7, 11, 13, 17, 29, 31, 37, 61])
 def test_every_launch_config(p):
     for k in sorted({min(p, 6), p}):
-        for (v, u, t) in _configs(p):
+        for (v, u, t, sp) in _configs(p):
             for w in (16, 64 * 4 * v + 16):
-                log(f"config p={p} k={k} vec={v} unroll={u} threads={t} W={w}")
-                r.raid6c_tune_set(p, 0, w, v, u, t)
-                r.raid6c_tune_set(p, 1, w, v, u, t)
+                log(f"config p={p} k={k} vec={v} unroll={u} threads={t} split={sp} W={w}")
+                r.raid6c_tune_set(p, 0, w, v, u, t, sp)
+                r.raid6c_tune_set(p, 1, w, v, u, t, sp)
                 want = _stripes(p, k, w, 4, seed=7 * p + v + t + u)
-                assert np.array_equal(_encode_on_gpu(want, p, k, w), want), (v, u, t, w)
+                assert np.array_equal(_encode_on_gpu(want, p, k, w), want), (v, u, t, sp, w)
                 er = datagen.erasures(v * 1000 + t + u, 4, k, "any")
-                assert np.array_equal(_recover_on_gpu(want, p, k, w, er), want), (v, u, t, w)
+                assert np.array_equal(_recover_on_gpu(want, p, k, w, er), want), (v, u, t, sp, w)
+                _single_stripe_calls(want[0], p, k, w, (v, u, t, sp, w))
+
+
+def _single_stripe_calls(stripe, p, k, w, tag):
+    """recover_2, recover_1 and read_degraded on one stripe: the erasures come
+    from the call's arguments, not from a device array."""
+    import torch
+    dev = to_dev(stripe)
+    strips = [dev[j] for j in range(k + 2)]
+    pairs = [(0, k), (k, k + 1)] + ([(0, 1)] if k > 1 else []) + [(k - 1, k + 1)]
+    for e0, e1 in pairs:
+        dev[e0] = to_dev(datagen.poison((p - 1, w), index=e0))
+        dev[e1] = to_dev(datagen.poison((p - 1, w), index=e1 + 64))
+        r.raid6c_recover_2(p, k, w, strips, e0, e1)
+        assert np.array_equal(to_host(dev), stripe), ("recover_2", e0, e1, tag)
+    for e in (0, k, k + 1):
+        dev[e] = to_dev(datagen.poison((p - 1, w), index=e + 128))
+        r.raid6c_recover_1(p, k, w, strips, e)
+        assert np.array_equal(to_host(dev), stripe), ("recover_1", e, tag)
+    out = torch.empty((2, p - 1, w), dtype=torch.uint8, device="cuda:0")
+    e0, e1 = pairs[-1]
+    out.fill_(0xEE)
+    r.raid6c_read_degraded(p, k, w, strips, e0, e1, out)
+    got = to_host(out)
+    assert np.array_equal(got[0], stripe[e0]) and np.array_equal(got[1], stripe[e1]), ("read", tag)
+    assert np.array_equal(to_host(dev), stripe), ("read wrote the stripe", tag)
 
 
 def test_config1_all_pairs():
@@ -223,13 +256,13 @@ def test_every_config_every_two_erasure_kind_many_stripes(p, w):
     k = p - 1
     n = 192
     want = zp.encode_stripe(datagen.fill_stripes(p, 0, n, k, p, w), p)
-    for (v, u, t) in _configs(p):
-        r.raid6c_tune_set(p, 0, w, v, u, t)
-        r.raid6c_tune_set(p, 1, w, v, u, t)
-        log(f"many stripes p={p} W={w} vec={v} unroll={u} threads={t}")
-        assert np.array_equal(_encode_on_gpu(want, p, k, w), want), ("encode", v, u, t)
+    for (v, u, t, sp) in _configs(p):
+        r.raid6c_tune_set(p, 0, w, v, u, t, sp)
+        r.raid6c_tune_set(p, 1, w, v, u, t, sp)
+        log(f"many stripes p={p} W={w} vec={v} unroll={u} threads={t} split={sp}")
+        assert np.array_equal(_encode_on_gpu(want, p, k, w), want), ("encode", v, u, t, sp)
         for kind in ("dd", "dp", "dq", "pq", "d"):
             er = datagen.erasures(p * 100 + v + u + t, n, k, kind)
             got = _recover_on_gpu(want, p, k, w, er)
             bad = [s for s in range(n) if not np.array_equal(got[s], want[s])]
-            assert not bad, (kind, v, u, t, bad[:5], [tuple(er[s]) for s in bad[:5]])
+            assert not bad, (kind, v, u, t, sp, bad[:5], [tuple(er[s]) for s in bad[:5]])
