@@ -190,14 +190,22 @@ def recover(stripe: np.ndarray, p: int, erased) -> np.ndarray:
 def update(stripe: np.ndarray, p: int, t: int, new_strip: np.ndarray) -> np.ndarray:
     """Stripe after data strip ``t`` is overwritten with ``new_strip``.
 
-    Its parity is, by definition, the parity of the new data (the Q-parity
-    update mentioned at the end of Section 3.4), so the oracle re-encodes.
+    The parity equations of Corollary 3.2.4 are linear, so a small write
+    updates the parity from the change alone (the Q-parity update that the
+    end of Section 3.4 prices at shifts, XOR and AND per power of S_N)::
+
+        dD = D_t + D_t',   P' = P + dD,   Q' = Q + g_t dD
+
+    with ``g_t = g^t`` (``Id + g^{t-p+1}`` for an extended strip ``t >= p``).
+    Only strips ``t``, P and Q change.
     """
     k = stripe.shape[-3] - 2
     _check(p, k, stripe.shape[-2])
     if not 0 <= t < k:
         raise ValueError("t must index a data strip")
-    data = stripe[..., :k, :, :].copy()
-    data[..., t, :, :] = new_strip
-    return encode_stripe(data, p)
-
+    out = stripe.copy()
+    delta = out[..., t, :, :] ^ new_strip
+    out[..., t, :, :] = new_strip
+    out[..., k, :, :] ^= delta
+    out[..., k + 1, :, :] ^= coefficient(delta, t, p)
+    return out

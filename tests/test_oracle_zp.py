@@ -246,13 +246,20 @@ def test_single_bit_flip_is_detected():
 
 
 def test_update_matches_reencode():
-    p, k, w = 11, 9, 8
-    data = _rand_data(p, k, w, 9)
-    stripe = zp.encode_stripe(data, p)
-    new = _rand_data(p, 1, w, 10)[0]
-    upd = zp.update(stripe, p, 4, new)
-    data[4] = new
-    assert (upd == zp.encode_stripe(data, p)).all()
+    # The small-write update (by linearity) against a full re-encode of the
+    # changed data: every data strip, plain and extended parity.
+    for p, k in ((11, 9), (7, 7), (5, 9), (13, 25)):
+        w = 8
+        data = _rand_data(p, k, w, 9 + k)
+        stripe = zp.encode_stripe(data, p)
+        for t in range(k):
+            new = _rand_data(p, 1, w, 100 + t)[0]
+            upd = zp.update(stripe, p, t, new)
+            changed = data.copy()
+            changed[t] = new
+            assert (upd == zp.encode_stripe(changed, p)).all(), (p, k, t)
+    with pytest.raises(ValueError):
+        zp.update(stripe, 13, 25, new)
 
 
 def test_argument_checks():
