@@ -206,6 +206,7 @@ def extras(reps, stream):
     del b
     torch.cuda.empty_cache()
     out["extended_q_parity"] = extended(reps, stream)
+    out["small_write_update"] = small_writes(reps, stream)
     out["batched_20000_mixed"] = batched_mixed(reps, stream)
     out["served_poisson"] = served_poisson()
     return out
@@ -243,6 +244,34 @@ def extended(reps, stream):
         out[f"p{p}_k{k}_w{w}_x{n}"] = res
         del b
         torch.cuda.empty_cache()
+    return out
+
+
+def small_writes(reps, stream):
+    """One data strip per stripe replaced, P and Q updated from the change
+    (7 strips moved per stripe), on the main workload's geometry; against a
+    re-encode of the whole batch ((k+2) strips per stripe)."""
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    b = r.StripeBatch.empty(P, K, W, NSTRIPES)
+    b.tensor.random_(0, 256)
+    src = torch.empty((NSTRIPES, P - 1, W), dtype=torch.uint8, device="cuda:0")
+    src.random_(0, 256)
+    d = datagen.Draws(7, datagen.TAG_ERASURE, 99)
+    targets = torch.tensor([d.below(K) for _ in range(NSTRIPES)], dtype=torch.int32, device="cuda:0")
+    ms = time_launches(lambda: b.update(targets, src), reps, stream)
+    enc = time_launches(lambda: b.encode(), reps, stream)
+    mean, emean = sum(ms) / len(ms), sum(enc) / len(enc)
+    moved = 7 * b.strip_stride * NSTRIPES
+    out = {"stripes": NSTRIPES, "new_bytes": b.strip_stride * NSTRIPES,
+           "GBps_new_data": round(b.strip_stride * NSTRIPES / (mean / 1e3) / 1e9, 1),
+           "hbm_frac": round(moved / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "ms_p50": round(pct(ms, 50), 4), "reencode_ms_p50": round(pct(enc, 50), 4),
+           "speedup_vs_reencode": round(emean / mean, 3)}
+    del b, src
+    torch.cuda.empty_cache()
     return out
 
 

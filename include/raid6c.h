@@ -175,6 +175,40 @@ int raid6c_read_degraded(int p, int k, size_t row_bytes, const void* const* stri
                          void* out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Small writes
+ * ------------------------------------------------------------------------ */
+
+/* Replace data strip t of one stripe with new_strip and update P and Q from
+ * the change alone: the parity equations (Corollary 3.2.4) are linear, so
+ * with dD = D_t + D_t'
+ *   P' = P + dD,   Q' = Q + g_t dD,
+ * g_t = g^t, or 1 + g^{t-p+1} for a strip t >= p of the extended Q parity
+ * (the Q-parity update that Section 3.4 prices at shifts and XORs).
+ * Reads strips[t], new_strip, strips[k], strips[k+1]; writes strips[t]
+ * (= new_strip), strips[k], strips[k+1]; no other strip is touched.  The
+ * stripe must be consistent before the call for the result to be.
+ *   strips    : host array of k+2 device pointers (entries other than t, k,
+ *               k+1 are not used and may be NULL)
+ *   new_strip : device, (p-1)*row_bytes bytes, must not overlap the strips
+ * Errors: as raid6c_encode, plus RAID6C_E_ARG for t not in [0, k) or a NULL,
+ * misaligned or overlapping strip. */
+int raid6c_update(int p, int k, size_t row_bytes, void* const* strips, int t,
+                  const void* new_strip, void* stream);
+
+/* Small writes on nstripes strided stripes: stripe s replaces data strip
+ * targets[s] (device int32 array) with the strip at src + s*src_stride,
+ * as raid6c_update.  An entry outside [0, k) leaves its stripe untouched and
+ * is counted into *bad_count (device int32, may be NULL).  The sources must
+ * not overlap the stripes.
+ * Errors: as raid6c_encode_n, plus RAID6C_E_ARG for NULL or misaligned
+ * targets or src, or src_stride below (p-1)*row_bytes or not a multiple of
+ * 16 (when nstripes > 1). */
+int raid6c_update_n(int p, int k, size_t row_bytes, void* base,
+                    size_t strip_stride, size_t stripe_stride, size_t nstripes,
+                    const int32_t* targets, const void* src, size_t src_stride,
+                    int32_t* bad_count, void* stream);
+
+/* ------------------------------------------------------------------------
  * Comparison code: Reed-Solomon RAID-6 over GF(256), polynomial 0x11D
  * ------------------------------------------------------------------------ */
 

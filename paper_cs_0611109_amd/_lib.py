@@ -39,6 +39,9 @@ SIGNATURES = {
     "raid6c_rs_encode_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
     "raid6c_rs_recover_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp, _vp, _vp]),
     "raid6c_rs_set_config": (_c_int, [_c_int, _c_int, _c_int]),
+    "raid6c_update": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_int, _vp, _vp]),
+    "raid6c_update_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp, _vp, _c_size, _vp,
+                                 _vp]),
     "raid6c_write": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, ctypes.POINTER(_vp), _vp]),
     "raid6c_read_degraded": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _c_int, _c_int, _vp, _vp]),
     "raid6c_vec_mask": (_c_int, [_c_int]),
@@ -258,6 +261,18 @@ def raid6c_rs_recover_n(k, strip_bytes, base, strip_stride, stripe_stride, nstri
                         bad_count=None, stream=None):
     return _check(load().raid6c_rs_recover_n(k, strip_bytes, _ptr(base), strip_stride, stripe_stride, nstripes,
                                              _ptr(erasures), _ptr(bad_count), _stream(stream)))
+
+
+def raid6c_update(p, k, row_bytes, strips, t, new_strip, stream=None):
+    """Small write: strip t of one stripe becomes ``new_strip``; P and Q follow."""
+    return _check(load().raid6c_update(p, k, row_bytes, _ptr_array(list(strips)), t, _ptr(new_strip),
+                                       _stream(stream)))
+
+
+def raid6c_update_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, targets, src, src_stride,
+                    bad_count=None, stream=None):
+    return _check(load().raid6c_update_n(p, k, row_bytes, _ptr(base), strip_stride, stripe_stride, nstripes,
+                                         _ptr(targets), _ptr(src), src_stride, _ptr(bad_count), _stream(stream)))
 
 
 def raid6c_rs_set_config(vec: int, unroll: int, threads: int) -> int:

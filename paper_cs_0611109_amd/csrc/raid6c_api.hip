@@ -401,6 +401,83 @@ int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base, size_t strip_strid
   return rs_run(k, strip_bytes, base, strip_stride, stripe_stride, nstripes, nullptr, nullptr, stream);
 }
 
+// Small writes (update.hip): launch over nstripes stripes, splitting the grid.
+static int launch_update(int p, UpdArgs a, size_t nstripes, void* stream) {
+  if (nstripes == 0) return RAID6C_OK;
+  const int vec = (p <= 13 && a.row_bytes >= 512) ? 2 : 1;
+  int threads = 64;
+  while (threads < 128 && (uint64_t)threads * vec * 4 < a.row_bytes) threads *= 2;
+  const uint64_t tile_bytes = (uint64_t)threads * vec * 4;
+  a.tiles = (uint32_t)((a.row_bytes + tile_bytes - 1) / tile_bytes);
+  const uint64_t chunk = (((uint64_t)1 << 31) / threads) / a.tiles;
+  size_t done = 0;
+  while (done < nstripes) {
+    const size_t n = (nstripes - done) < chunk ? (nstripes - done) : chunk;
+    UpdArgs b = a;
+    if (done != 0) {
+      b.base = a.base + done * a.stripe_stride;
+      b.src = a.src + done * a.src_stride;
+      if (a.targets != nullptr) b.targets = a.targets + done;
+    }
+    b.nstripes = (uint32_t)n;
+    const hipError_t err = update_launch(b, p, vec, threads, (uint32_t)(n * a.tiles), (hipStream_t)stream);
+    if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    done += n;
+  }
+  return RAID6C_OK;
+}
+
+int raid6c_update(int p, int k, size_t row_bytes, void* const* strips, int t, const void* new_strip, void* stream) {
+  g_last_error.clear();
+  int rc = check_geometry(p, k, row_bytes);
+  if (rc != RAID6C_OK) return rc;
+  if (t < 0 || t >= k) return fail(RAID6C_E_ARG, "t = %d must index a data strip (0..%d)", t, k - 1);
+  if (strips == nullptr) return fail(RAID6C_E_ARG, "strip pointer array is NULL");
+  const size_t strip = (size_t)(p - 1) * row_bytes;
+  const void* ptrs[4] = {strips[t], strips[k], strips[k + 1], new_strip};
+  rc = check_strip_ptrs(4, ptrs, strip);
+  if (rc != RAID6C_OK) return rc;
+  UpdArgs a;
+  memset(&a, 0, sizeof a);
+  a.pd = (uint8_t*)strips[t];
+  a.pp = (uint8_t*)strips[k];
+  a.pq = (uint8_t*)strips[k + 1];
+  a.src = (const uint8_t*)new_strip;
+  a.row_bytes = row_bytes;
+  a.t = t;
+  a.k = k;
+  return launch_update(p, a, 1, stream);
+}
+
+int raid6c_update_n(int p, int k, size_t row_bytes, void* base, size_t strip_stride, size_t stripe_stride,
+                    size_t nstripes, const int32_t* targets, const void* src, size_t src_stride, int32_t* bad_count,
+                    void* stream) {
+  g_last_error.clear();
+  int rc = check_strided(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes);
+  if (rc != RAID6C_OK) return rc;
+  if (nstripes == 0) return RAID6C_OK;
+  if (targets == nullptr || ((uintptr_t)targets & 3u) != 0)
+    return fail(RAID6C_E_ARG, "targets is NULL or not 4-byte aligned");
+  const size_t strip = (size_t)(p - 1) * row_bytes;
+  if (src == nullptr || !aligned16(src)) return fail(RAID6C_E_ARG, "src is NULL or not 16-byte aligned");
+  if (nstripes > 1 && ((src_stride % 16) != 0 || src_stride < strip))
+    return fail(RAID6C_E_ARG, "src_stride = %zu must be a multiple of 16 and >= (p-1)*row_bytes = %zu", src_stride,
+                strip);
+  UpdArgs a;
+  memset(&a, 0, sizeof a);
+  a.base = (uint8_t*)base;
+  a.strip_stride = strip_stride;
+  a.stripe_stride = stripe_stride;
+  a.src = (const uint8_t*)src;
+  a.src_stride = src_stride;
+  a.targets = targets;
+  a.bad_count = bad_count;
+  a.row_bytes = row_bytes;
+  a.t = -1;
+  a.k = k;
+  return launch_update(p, a, nstripes, stream);
+}
+
 int raid6c_rs_set_config(int vec, int unroll, int threads) {
   g_last_error.clear();
   if (!set_rs_override(vec, unroll, threads))

@@ -168,4 +168,24 @@ struct RsArgs {
 };
 hipError_t rs_launch(const RsArgs& a, int vec, int unroll, int threads, uint32_t grid, hipStream_t stream);
 
+// Small-write kernels (update.hip).
+struct UpdArgs {
+  uint8_t* base;               // strided stripes (strip j of stripe s at base + s*stripe_stride +
+  uint64_t strip_stride;       // j*strip_stride), or NULL for one stripe given by pd, pp, pq
+  uint64_t stripe_stride;
+  uint8_t* pd;                 // one stripe: data strip t, P and Q
+  uint8_t* pp;
+  uint8_t* pq;
+  const uint8_t* src;          // new data strip of stripe s at src + s*src_stride
+  uint64_t src_stride;
+  const int32_t* targets;      // per-stripe data strip index (device), or NULL: `t` for all
+  int32_t* bad_count;          // device counter of rejected entries, or NULL
+  uint64_t row_bytes;
+  uint32_t nstripes;
+  uint32_t tiles;
+  int32_t t;
+  int32_t k;
+};
+hipError_t update_launch(const UpdArgs& a, int p, int vec, int threads, uint32_t grid, hipStream_t stream);
+
 }  // namespace raid6c

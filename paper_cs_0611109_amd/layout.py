@@ -58,6 +58,13 @@ class StripeBatch:
         return _lib.raid6c_autotune_n(self.p, self.k, self.row_bytes, self.tensor.data_ptr(), self.strip_stride,
                                       self.stripe_stride, self.nstripes, op, erasures, reps, stream)
 
+    def update(self, targets, src, src_stride=None, bad_count=None, stream=None):
+        """Small writes: stripe s replaces data strip targets[s] (device int32)
+        with the strip at ``src`` + s*src_stride; P and Q follow."""
+        ss = self.strip_stride if src_stride is None else src_stride
+        return _lib.raid6c_update_n(self.p, self.k, self.row_bytes, self.tensor.data_ptr(), self.strip_stride,
+                                    self.stripe_stride, self.nstripes, targets, src, ss, bad_count, stream)
+
     def rs_encode(self, stream=None):
         """Reed-Solomon GF(256) P+Q over the same bytes (each strip a byte vector)."""
         return _lib.raid6c_rs_encode_n(self.k, self.strip_stride, self.tensor.data_ptr(), self.strip_stride,

@@ -120,6 +120,21 @@ def test_encode_single_argument_checks():
          stream=0)
 
 
+def test_update_argument_checks():
+    strips = [FAKE + i * 4096 for i in range(6)]
+    new = FAKE + 100 * 4096
+    _err(r.raid6c_update, 5, 4, 64, strips, 4, new, stream=0)            # t = P
+    _err(r.raid6c_update, 5, 4, 64, strips, -1, new, stream=0)
+    _err(r.raid6c_update, 5, 4, 64, strips, 1, strips[4] + 64, stream=0)   # new overlaps P
+    _err(r.raid6c_update, 5, 4, 64, strips, 1, 0, stream=0)
+    _err(r.raid6c_update, 5, 4, 24, strips, 1, new, stream=0)
+    _err(r.raid6c_update_n, 5, 4, 64, FAKE, 256, 1536, 4, 0, new, 256, stream=0)        # NULL targets
+    _err(r.raid6c_update_n, 5, 4, 64, FAKE, 256, 1536, 4, FAKE + 2, new, 256, stream=0)
+    _err(r.raid6c_update_n, 5, 4, 64, FAKE, 256, 1536, 4, FAKE, 0, 256, stream=0)       # NULL src
+    _err(r.raid6c_update_n, 5, 4, 64, FAKE, 256, 1536, 4, FAKE, new, 128, stream=0)     # src stride
+    assert r.raid6c_update_n(5, 4, 64, FAKE, 256, 1536, 0, 0, 0, 0, stream=0) == 0      # empty call
+
+
 def test_rs_argument_checks():
     _err(r.raid6c_rs_encode_n, 0, 64, FAKE, 64, 64 * 4, 1, stream=0)
     _err(r.raid6c_rs_encode_n, 256, 64, FAKE, 64, 64 * 258, 1, stream=0)
