@@ -207,6 +207,7 @@ def extras(reps, stream):
     torch.cuda.empty_cache()
     out["extended_q_parity"] = extended(reps, stream)
     out["small_write_update"] = small_writes(reps, stream)
+    out["z17_horizontal_interop"] = z17_interop(reps, stream)
     out["batched_20000_mixed"] = batched_mixed(reps, stream)
     out["served_poisson"] = served_poisson()
     return out
@@ -271,6 +272,31 @@ def small_writes(reps, stream):
            "ms_p50": round(pct(ms, 50), 4), "reencode_ms_p50": round(pct(enc, 50), 4),
            "speedup_vs_reencode": round(emean / mean, 3)}
     del b, src
+    torch.cuda.empty_cache()
+    return out
+
+
+def z17_interop(reps, stream):
+    """Conversion between the paper's horizontal Z_17 layout (one codeword per
+    int16) and vertical strips: 2 GiB of strips each way; bytes moved = read
+    + written."""
+    import torch
+
+    import paper_cs_0611109_amd as r
+    w, count = 4096, 16384                         # 16384 strips of 64 KiB
+    h = torch.empty((count, 8 * w), dtype=torch.int16, device="cuda:0")
+    h.random_(-32768, 32767)
+    v = torch.empty((count, 16, w), dtype=torch.uint8, device="cuda:0")
+    moved = 2 * 16 * w * count
+    to_v = time_launches(lambda: r.raid6c_z17_to_vertical(h, w, count, v), reps, stream)
+    to_h = time_launches(lambda: r.raid6c_z17_to_horizontal(v, w, count, h), reps, stream)
+    out = {}
+    for name, ms in (("to_vertical", to_v), ("to_horizontal", to_h)):
+        mean = sum(ms) / len(ms)
+        out[name] = {"GBps_moved": round(moved / (mean / 1e3) / 1e9, 1),
+                     "hbm_frac": round(moved / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "ms_p50": round(pct(ms, 50), 4)}
+    del h, v
     torch.cuda.empty_cache()
     return out
 

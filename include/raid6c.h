@@ -209,6 +209,26 @@ int raid6c_update_n(int p, int k, size_t row_bytes, void* base,
                     int32_t* bad_count, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's horizontal Z_17 layout
+ *
+ * Section 4.5 keeps one codeword of R_17 per 16-bit word, bit r being the
+ * coefficient of x^r (so that g.x = (x + x) ^ (x < 0 ? 0xffff : 0)).  A
+ * horizontal strip of 8*row_bytes words and a vertical strip of 16 rows of
+ * row_bytes bytes hold the same codewords when codeword c is lane
+ * (byte c/8, bit c%8) of the vertical strip; parity computed in either
+ * layout is the same after conversion.
+ * ------------------------------------------------------------------------ */
+
+/* Convert `count` consecutive horizontal strips (words + s*8*row_bytes
+ * uint16, device) into vertical strips (strips + s*16*row_bytes, row r at
+ * r*row_bytes, device).  row_bytes: a positive multiple of 16; buffers
+ * 16-byte aligned and not overlapping.  Errors: RAID6C_E_ARG. */
+int raid6c_z17_to_vertical(const void* words, size_t row_bytes, size_t count, void* strips, void* stream);
+
+/* The inverse conversion, same layouts and errors. */
+int raid6c_z17_to_horizontal(const void* strips, size_t row_bytes, size_t count, void* words, void* stream);
+
+/* ------------------------------------------------------------------------
  * Comparison code: Reed-Solomon RAID-6 over GF(256), polynomial 0x11D
  * ------------------------------------------------------------------------ */
 

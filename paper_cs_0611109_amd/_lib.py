@@ -39,6 +39,8 @@ SIGNATURES = {
     "raid6c_rs_encode_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp]),
     "raid6c_rs_recover_n": (_c_int, [_c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp, _vp, _vp]),
     "raid6c_rs_set_config": (_c_int, [_c_int, _c_int, _c_int]),
+    "raid6c_z17_to_vertical": (_c_int, [_vp, _c_size, _c_size, _vp, _vp]),
+    "raid6c_z17_to_horizontal": (_c_int, [_vp, _c_size, _c_size, _vp, _vp]),
     "raid6c_update": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_int, _vp, _vp]),
     "raid6c_update_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _vp, _vp, _c_size, _vp,
                                  _vp]),
@@ -261,6 +263,15 @@ def raid6c_rs_recover_n(k, strip_bytes, base, strip_stride, stripe_stride, nstri
                         bad_count=None, stream=None):
     return _check(load().raid6c_rs_recover_n(k, strip_bytes, _ptr(base), strip_stride, stripe_stride, nstripes,
                                              _ptr(erasures), _ptr(bad_count), _stream(stream)))
+
+
+def raid6c_z17_to_vertical(words, row_bytes, count, strips, stream=None):
+    """Horizontal Z_17 strips (one codeword per uint16) -> vertical strips."""
+    return _check(load().raid6c_z17_to_vertical(_ptr(words), row_bytes, count, _ptr(strips), _stream(stream)))
+
+
+def raid6c_z17_to_horizontal(strips, row_bytes, count, words, stream=None):
+    return _check(load().raid6c_z17_to_horizontal(_ptr(strips), row_bytes, count, _ptr(words), _stream(stream)))
 
 
 def raid6c_update(p, k, row_bytes, strips, t, new_strip, stream=None):

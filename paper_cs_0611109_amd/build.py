@@ -29,7 +29,7 @@ CFLAGS = [
 ]
 
 # Plain (non-templated-per-prime) sources.
-SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip", "update.hip", "batch.hip", "serve.hip"]
+SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip", "update.hip", "layout.hip", "batch.hip", "serve.hip"]
 
 
 def _units(build_dir):

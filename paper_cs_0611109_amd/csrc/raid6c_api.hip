@@ -478,6 +478,31 @@ int raid6c_update_n(int p, int k, size_t row_bytes, void* base, size_t strip_str
   return launch_update(p, a, nstripes, stream);
 }
 
+static int z17_convert(bool to_vertical, const void* in, size_t row_bytes, size_t count, void* out, void* stream) {
+  g_last_error.clear();
+  if (row_bytes == 0 || (row_bytes % 16) != 0)
+    return fail(RAID6C_E_ARG, "row_bytes = %zu must be a positive multiple of 16", row_bytes);
+  if (count == 0) return RAID6C_OK;
+  if (in == nullptr || out == nullptr || !aligned16(in) || !aligned16(out))
+    return fail(RAID6C_E_ARG, "a buffer is NULL or not 16-byte aligned");
+  const size_t bytes = 16 * row_bytes;           // per strip, in either layout
+  if (count > ((size_t)1 << 40) / bytes) return fail(RAID6C_E_ARG, "count * 16 * row_bytes is too large");
+  const uintptr_t a0 = (uintptr_t)in, b0 = (uintptr_t)out;
+  if (a0 < b0 + count * bytes && b0 < a0 + count * bytes)
+    return fail(RAID6C_E_ARG, "input and output overlap");
+  const hipError_t err = z17_launch(to_vertical, in, out, row_bytes, count, (hipStream_t)stream);
+  if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+  return RAID6C_OK;
+}
+
+int raid6c_z17_to_vertical(const void* words, size_t row_bytes, size_t count, void* strips, void* stream) {
+  return z17_convert(true, words, row_bytes, count, strips, stream);
+}
+
+int raid6c_z17_to_horizontal(const void* strips, size_t row_bytes, size_t count, void* words, void* stream) {
+  return z17_convert(false, strips, row_bytes, count, words, stream);
+}
+
 int raid6c_rs_set_config(int vec, int unroll, int threads) {
   g_last_error.clear();
   if (!set_rs_override(vec, unroll, threads))

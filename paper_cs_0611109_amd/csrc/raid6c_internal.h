@@ -188,4 +188,9 @@ struct UpdArgs {
 };
 hipError_t update_launch(const UpdArgs& a, int p, int vec, int threads, uint32_t grid, hipStream_t stream);
 
+// Horizontal Z_17 layout <-> vertical strips (layout.hip): count strips of
+// 8*row_bytes 16-bit words <-> count strips of 16 rows of row_bytes bytes.
+hipError_t z17_launch(bool to_vertical, const void* in, void* out, uint64_t row_bytes, uint64_t count,
+                      hipStream_t stream);
+
 }  // namespace raid6c

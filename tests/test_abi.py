@@ -135,6 +135,14 @@ def test_update_argument_checks():
     assert r.raid6c_update_n(5, 4, 64, FAKE, 256, 1536, 0, 0, 0, 0, stream=0) == 0      # empty call
 
 
+def test_z17_argument_checks():
+    _err(r.raid6c_z17_to_vertical, FAKE, 24, 1, FAKE + (1 << 20), stream=0)          # row bytes
+    _err(r.raid6c_z17_to_vertical, FAKE + 8, 64, 1, FAKE + (1 << 20), stream=0)      # alignment
+    _err(r.raid6c_z17_to_vertical, FAKE, 64, 4, FAKE + 1024, stream=0)               # overlap
+    _err(r.raid6c_z17_to_horizontal, 0, 64, 1, FAKE, stream=0)
+    assert r.raid6c_z17_to_vertical(FAKE, 64, 0, FAKE, stream=0) == 0                 # empty call
+
+
 def test_rs_argument_checks():
     _err(r.raid6c_rs_encode_n, 0, 64, FAKE, 64, 64 * 4, 1, stream=0)
     _err(r.raid6c_rs_encode_n, 256, 64, FAKE, 64, 64 * 258, 1, stream=0)
