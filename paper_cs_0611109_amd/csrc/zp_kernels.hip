@@ -125,12 +125,26 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
   const uint32_t strip_bytes = (uint32_t)((P - 1) * a.row_bytes);
   const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
                     strip_bytes};
-  const int per = (k + S - 1) / S;
-  const int t0 = w * per;
-  const int t1 = t0 + per < k ? t0 + per : k;
   // Erased data strips are skipped; P/Q are rebuilt, never read, in their cases.
   const int x = (cs.op == OP_D || cs.op == OP_DP || cs.op == OP_DQ || cs.op == OP_DD) ? cs.x : -1;
   const int y = cs.op == OP_DD ? cs.y : -1;
+  const bool add_p = cs.op == OP_D || cs.op == OP_DQ || cs.op == OP_DD;
+  const bool add_q = cs.op == OP_DP || cs.op == OP_DD;
+  // Balanced contiguous ranges: the strips a wave loads (surviving data
+  // strips, and for wave 0 also P and/or Q) are split evenly.  pos(m) is the
+  // first t with m surviving data strips below it.
+  const int surv = k - (x >= 0) - (y >= 0);
+  const int extra = (int)add_p + (int)add_q;
+  const int per = (surv + extra + S - 1) / S;
+  auto pos = [&](int m) {
+    int t = m;
+    if (x >= 0 && x < t) ++t;
+    if (y >= 0 && y < t) ++t;
+    return t;
+  };
+  auto clampm = [&](int m) { return m < 0 ? 0 : (m > surv ? surv : m); };
+  const int t0 = pos(clampm(w * per - extra));
+  const int t1 = pos(clampm((w + 1) * per - extra));
   VT ap[R], aq[P];
 #pragma unroll
   for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
@@ -138,9 +152,9 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
   for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
   if (live) {
     if (t0 < t1) stream_range<P, V, U, true, true>(c, t1 - 1, t0, x, y, ap, aq);
-    if (w == 0) {
-      if (cs.op == OP_D || cs.op == OP_DQ || cs.op == OP_DD) xor_from<P, V>(c, k, ap);
-      if (cs.op == OP_DP || cs.op == OP_DD) xor_from<P, V>(c, k + 1, aq);
+    if (w == 0) {   // t0 = 0 here, so Q enters unrotated
+      if (add_p) xor_from<P, V>(c, k, ap);
+      if (add_q) xor_from<P, V>(c, k + 1, aq);
     }
   }
   uint32_t* my = part + (size_t)w * NR * CS + lane * V;
