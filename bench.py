@@ -367,8 +367,9 @@ def served_poisson(n=4000, seed=5):
 def batched_mixed(reps, stream):
     """20,000 stripes of mixed geometry (p from {5,11,13,19,29,37,53}, k
     uniform in [2, p-1], rows log-uniform over 512 B..64 KiB; 60% encode, 40%
-    two-erasure recovery): one plan run (a persistent kernel in a HIP graph)
-    against the same jobs as 20,000 plain launches on one stream."""
+    two-erasure recovery): one plan run (a HIP graph: one job-list grid per
+    prime, or one persistent kernel, whichever the autotuner picks) against
+    the same jobs as 20,000 plain launches on one stream."""
     import torch
 
     import datagen
@@ -393,6 +394,13 @@ def batched_mixed(reps, stream):
         tuned_ms = r.raid6c_plan_autotune(plan, reps=2)
         sched = r.raid6c_plan_get_schedule(plan)
         plan_ms = time_launches(lambda: r.raid6c_plan_run(plan), reps, stream)
+        # Both execution modes on their own, for the record.
+        modes = {}
+        for name, cand in (("grouped", (8, 4, 0, 1)), ("persistent", (8, 4, 0, 0))):
+            r.raid6c_plan_set_schedule(plan, *cand)
+            ms_m = time_launches(lambda: r.raid6c_plan_run(plan), max(3, reps // 2), stream)
+            modes[name] = round(sum(ms_m) / len(ms_m), 3)
+        r.raid6c_plan_set_schedule(plan, sched.waves_per_cu, sched.chunk, sched.order, sched.grouped)
         plain_ms = time_launches(lambda: r.raid6c_run_jobs(arr), max(3, reps // 5), stream)
     finally:
         r.raid6c_plan_destroy(plan)
@@ -410,8 +418,10 @@ def batched_mixed(reps, stream):
         "plain_launches_ms_mean": round(qm, 3),
         "plain_GBps_user": round(info.user_bytes / (qm / 1e3) / 1e9, 1),
         "speedup_vs_plain": round(qm / pm, 3),
-        "schedule": {"waves_per_cu": sched.waves_per_cu, "chunk": sched.chunk, "order": sched.order},
+        "schedule": {"waves_per_cu": sched.waves_per_cu, "chunk": sched.chunk, "order": sched.order,
+                     "grouped": sched.grouped},
         "autotune_best_ms": round(tuned_ms, 3),
+        "mode_ms_mean": modes,
     }
 
 

@@ -299,12 +299,20 @@ typedef struct raid6c_job {
 #define RAID6C_ORDER_BY_PRIME      1  /* grouped by p (largest p first) */
 #define RAID6C_ORDER_SUBMITTED     2  /* job order as given */
 
-/* Schedule of a plan: persistent work-groups per compute unit, work items
- * taken per counter increment, and item order.  Changes speed only. */
+/* Schedule of a plan.  Changes speed only.
+ *  grouped = 1 (the default): the jobs of each prime run as one grid of a
+ *    job-list kernel compiled for that prime (tiles of 64 lanes x 2 dwords
+ *    for p <= 29, x 1 dword above; 4 waves per work-group, one tile each);
+ *    the grids are independent nodes of the plan's graph.  The other fields
+ *    are kept but unused.
+ *  grouped = 0: one persistent kernel for all primes; waves_per_cu
+ *    persistent work-groups per compute unit take `chunk` 256-byte tiles per
+ *    increment of a device counter, in `order`. */
 typedef struct raid6c_schedule {
   int32_t waves_per_cu;  /* 1..32 */
   int32_t chunk;         /* 1..1024 */
   int32_t order;         /* RAID6C_ORDER_* */
+  int32_t grouped;       /* 0 or 1 */
 } raid6c_schedule;
 
 typedef struct raid6c_plan_info {
@@ -313,7 +321,7 @@ typedef struct raid6c_plan_info {
   uint64_t bytes_moved;  /* algorithmic HBM bytes per run */
   uint64_t user_bytes;   /* sum of k*(p-1)*row_bytes */
   int32_t max_p;
-  int32_t grid;          /* persistent work-groups per launch */
+  int32_t grid;          /* work-groups per run (all grids of a grouped run) */
 } raid6c_plan_info;
 
 typedef struct raid6c_plan raid6c_plan;
@@ -341,7 +349,8 @@ int raid6c_plan_set_schedule(raid6c_plan* plan, const raid6c_schedule* schedule)
 /* Sizes of the plan.  Errors: RAID6C_E_ARG for NULL arguments. */
 int raid6c_plan_stats(const raid6c_plan* plan, raid6c_plan_info* out);
 
-/* Autotuner: time every candidate schedule (waves per CU x chunk x order)
+/* Autotuner: time every candidate schedule (grouped, and the persistent
+ * kernel with waves per CU x chunk x order)
  * over `reps` runs each on `stream`, keep the fastest, and return its mean
  * time per run in *best_ms (may be NULL).  Runs the plan (reps+1) times per
  * candidate, which rewrites the same output bytes.  Synchronises.

@@ -82,7 +82,8 @@ class raid6c_job(ctypes.Structure):
 
 
 class raid6c_schedule(ctypes.Structure):
-    _fields_ = [("waves_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32), ("order", ctypes.c_int32)]
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("grouped", ctypes.c_int32)]
 
 
 class raid6c_plan_info(ctypes.Structure):
@@ -337,8 +338,8 @@ def raid6c_plan_get_schedule(plan) -> raid6c_schedule:
     return s
 
 
-def raid6c_plan_set_schedule(plan, waves_per_cu, chunk, order):
-    s = raid6c_schedule(waves_per_cu, chunk, order)
+def raid6c_plan_set_schedule(plan, waves_per_cu, chunk, order, grouped=0):
+    s = raid6c_schedule(waves_per_cu, chunk, order, grouped)
     return _check(load().raid6c_plan_set_schedule(plan, ctypes.byref(s)))
 
 

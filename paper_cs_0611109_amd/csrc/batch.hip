@@ -131,10 +131,19 @@ using namespace raid6c;
 struct raid6c_plan {
   int device = 0;
   std::vector<BatchJob> jobs;
-  std::vector<BatchItem> items;   // current order
+  std::vector<BatchItem> items;   // current order (persistent kernel, 256-byte tiles)
   std::vector<uint64_t> job_cost; // bytes moved per tile, per job
-  void* dmem = nullptr;           // jobs | items | counter
+  void* dmem = nullptr;           // jobs | items | counter | group items
   BatchArgs args{};
+  // Grouped schedule: one job-list grid per prime, as independent graph nodes.
+  struct Group {
+    int p;
+    uint32_t first, n;            // range in gitems
+  };
+  std::vector<BatchItem> gitems;  // per prime, tiles of 64 lanes x that prime's group_vec dwords
+  std::vector<Group> groups;
+  std::vector<GroupArgs> gargs;
+  const BatchItem* d_gitems = nullptr;
   int max_p = 3;
   int cus = 256;
   raid6c_schedule sched{};
@@ -166,6 +175,29 @@ void order_items(raid6c_plan* pl, int order) {
   }
 }
 
+// Items of the grouped schedule: jobs of one prime together (largest p first,
+// costliest stripes first within a prime), each job's tiles consecutive.
+void group_items(raid6c_plan* pl) {
+  const size_t nj = pl->jobs.size();
+  std::vector<uint32_t> idx(nj);
+  for (size_t i = 0; i < nj; ++i) idx[i] = (uint32_t)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+    if (pl->jobs[a].p != pl->jobs[b].p) return pl->jobs[a].p > pl->jobs[b].p;
+    return pl->job_cost[a] > pl->job_cost[b];
+  });
+  pl->gitems.clear();
+  pl->groups.clear();
+  for (uint32_t j : idx) {
+    const int p = pl->jobs[j].p;
+    if (pl->groups.empty() || pl->groups.back().p != p)
+      pl->groups.push_back(raid6c_plan::Group{p, (uint32_t)pl->gitems.size(), 0});
+    const uint32_t tile = 64u * 4u * (uint32_t)zp_prime_entry(p)->group_vec;
+    const uint32_t w = pl->jobs[j].row_bytes;
+    for (uint32_t c = 0; c < w; c += tile) pl->gitems.push_back(BatchItem{j, c});
+    pl->groups.back().n = (uint32_t)pl->gitems.size() - pl->groups.back().first;
+  }
+}
+
 void free_graph(raid6c_plan* pl) {
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
@@ -177,12 +209,34 @@ void free_graph(raid6c_plan* pl) {
 // schedule.
 int build_graph(raid6c_plan* pl) {
   free_graph(pl);
-  hipError_t e = hipMemcpy((void*)pl->args.items, pl->items.data(), pl->items.size() * sizeof(BatchItem),
-                           hipMemcpyHostToDevice);
-  if (e != hipSuccess) return fail(RAID6C_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
-  pl->args.chunk = (uint32_t)pl->sched.chunk;
+  hipError_t e;
   if ((e = hipGraphCreate(&pl->graph, 0)) != hipSuccess)
     return fail(RAID6C_E_HIP, "hipGraphCreate: %s", hipGetErrorString(e));
+  if (pl->sched.grouped) {
+    // One node per prime, no edges: the grids may run side by side.
+    pl->gargs.clear();
+    for (const auto& g : pl->groups) pl->gargs.push_back(GroupArgs{pl->args.jobs, pl->d_gitems + g.first, g.n});
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
+      const raid6c_plan::Group& g = pl->groups[gi];
+      hipGraphNode_t node;
+      void* params[] = {(void*)&pl->gargs[gi]};
+      hipKernelNodeParams kp{};
+      kp.func = (void*)zp_prime_entry(g.p)->group_kernel;
+      kp.gridDim = dim3((g.n + 3) / 4);
+      kp.blockDim = dim3(256);
+      kp.sharedMemBytes = (unsigned)(g.p * 256 * 4);
+      kp.kernelParams = params;
+      if ((e = hipGraphAddKernelNode(&node, pl->graph, nullptr, 0, &kp)) != hipSuccess)
+        return fail(RAID6C_E_HIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+    }
+    if ((e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0)) != hipSuccess)
+      return fail(RAID6C_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return RAID6C_OK;
+  }
+  e = hipMemcpy((void*)pl->args.items, pl->items.data(), pl->items.size() * sizeof(BatchItem),
+                hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(RAID6C_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
+  pl->args.chunk = (uint32_t)pl->sched.chunk;
 
   hipGraphNode_t reset_node, batch_node;
   void* reset_params[] = {(void*)&pl->args.counter};
@@ -237,7 +291,8 @@ int check_job(const raid6c_job& J, size_t i, Case* out) {
 bool valid_schedule(const raid6c_schedule& s) {
   return s.waves_per_cu >= 1 && s.waves_per_cu <= 32 && s.chunk >= 1 && s.chunk <= 1024 &&
          (s.order == RAID6C_ORDER_LARGEST_FIRST || s.order == RAID6C_ORDER_BY_PRIME ||
-          s.order == RAID6C_ORDER_SUBMITTED);
+          s.order == RAID6C_ORDER_SUBMITTED) &&
+         (s.grouped == 0 || s.grouped == 1);
 }
 
 }  // namespace
@@ -311,16 +366,18 @@ int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) 
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) == hipSuccess && cus > 0)
     pl->cus = cus;
-  pl->sched = raid6c_schedule{8, 4, RAID6C_ORDER_LARGEST_FIRST};
+  pl->sched = raid6c_schedule{8, 4, RAID6C_ORDER_LARGEST_FIRST, 1};
   order_items(pl, pl->sched.order);
-  if (pl->items.size() > 0xFFFFFFFFull) {
+  group_items(pl);
+  if (pl->items.size() > 0xFFFFFFFFull || pl->gitems.size() > 0xFFFFFFFFull) {
     delete pl;
     return fail(RAID6C_E_ARG, "too many work items");
   }
 
   const size_t jb = std::max<size_t>(1, pl->jobs.size()) * sizeof(BatchJob);
   const size_t ib = std::max<size_t>(1, pl->items.size()) * sizeof(BatchItem);
-  const size_t total = jb + ib + 256;
+  const size_t gb = std::max<size_t>(1, pl->gitems.size()) * sizeof(BatchItem);
+  const size_t total = jb + ib + 256 + gb;
   hipError_t e = hipMalloc(&pl->dmem, total);
   if (e != hipSuccess) {
     delete pl;
@@ -329,11 +386,15 @@ int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) 
   pl->args.jobs = (const BatchJob*)pl->dmem;
   pl->args.items = (const BatchItem*)((uint8_t*)pl->dmem + jb);
   pl->args.counter = (uint64_t*)((uint8_t*)pl->dmem + jb + ib);
+  pl->d_gitems = (const BatchItem*)((uint8_t*)pl->dmem + jb + ib + 256);
   pl->args.base = 0;
   pl->args.nitems = (uint32_t)pl->items.size();
-  if (!pl->jobs.empty() &&
-      (e = hipMemcpy((void*)pl->args.jobs, pl->jobs.data(), pl->jobs.size() * sizeof(BatchJob),
-                     hipMemcpyHostToDevice)) != hipSuccess) {
+  if ((!pl->jobs.empty() &&
+       (e = hipMemcpy((void*)pl->args.jobs, pl->jobs.data(), pl->jobs.size() * sizeof(BatchJob),
+                      hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!pl->gitems.empty() &&
+       (e = hipMemcpy((void*)pl->d_gitems, pl->gitems.data(), pl->gitems.size() * sizeof(BatchItem),
+                      hipMemcpyHostToDevice)) != hipSuccess)) {
     (void)hipFree(pl->dmem);
     delete pl;
     return fail(RAID6C_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
@@ -365,6 +426,9 @@ int raid6c_plan_set_schedule(raid6c_plan* plan, const raid6c_schedule* s) {
   if (plan == nullptr || s == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
   if (!valid_schedule(*s)) return fail(RAID6C_E_ARG, "invalid schedule");
   const bool reorder = s->order != plan->sched.order;
+  // A persistent-kernel replay reads the item order from device memory:
+  // finish the runs in flight before it is rewritten.
+  if (reorder) (void)hipDeviceSynchronize();
   plan->sched = *s;
   if (reorder) order_items(plan, s->order);
   return build_graph(plan);
@@ -377,7 +441,9 @@ int raid6c_plan_stats(const raid6c_plan* plan, raid6c_plan_info* out) {
   out->bytes_moved = plan->bytes;
   out->user_bytes = plan->user_bytes;
   out->max_p = plan->max_p;
-  out->grid = plan->cus * plan->sched.waves_per_cu;
+  uint64_t wgs = 0;
+  for (const auto& g : plan->groups) wgs += (g.n + 3) / 4;
+  out->grid = plan->sched.grouped ? (uint32_t)wgs : (uint32_t)(plan->cus * plan->sched.waves_per_cu);
   return RAID6C_OK;
 }
 
@@ -398,10 +464,13 @@ int raid6c_plan_autotune(raid6c_plan* plan, void* stream, int reps, float* best_
   raid6c_schedule best = plan->sched;
   float best_t = 1e30f;
   int rc = RAID6C_OK;
-  for (int o : orders) {
-    for (int w : waves) {
-      for (int c : chunks) {
-        const raid6c_schedule cand{w, c, o};
+  // The grouped schedule, then every persistent-kernel candidate.
+  for (int gi = 0; gi < 1 + 2 * 4 * 3; ++gi) {
+    {
+      {
+        const raid6c_schedule cand = gi == 0 ? raid6c_schedule{8, 4, RAID6C_ORDER_LARGEST_FIRST, 1}
+                                             : raid6c_schedule{waves[((gi - 1) / 3) % 4], chunks[(gi - 1) % 3],
+                                                               orders[(gi - 1) / 12], 0};
         if ((rc = raid6c_plan_set_schedule(plan, &cand)) != RAID6C_OK) goto done;
         if ((rc = raid6c_plan_run(plan, stream)) != RAID6C_OK) goto done;  // warm-up
         (void)hipEventRecord(e0, s);

@@ -86,6 +86,16 @@ enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
 // configuration that is not built).
 typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a,
                                  uint32_t grid, hipStream_t stream);
+
+struct BatchJob;
+struct BatchItem;
+// A plan's jobs of one prime run as one grid of the per-prime job-list
+// kernel (zp_kernels.hip, variant 3): work-groups of 4 waves, one item each.
+struct GroupArgs {
+  const BatchJob* jobs;
+  const BatchItem* items;    // this group's items (tiles of 64 lanes x group_vec dwords)
+  uint32_t nitems;
+};
 struct ZpPrimeEntry {
   int p;
   ZpLauncher launch;       // plain code, k <= p (split-K configurations included)
@@ -93,6 +103,8 @@ struct ZpPrimeEntry {
   int vec_mask;        // bit v set when vec = v is instantiated (bits 1, 2, 4)
   int unroll_mask[5];  // per vec: bit u set when (vec, unroll = u) is instantiated
   int split_mask[5];   // per vec: bit s set when split = s (2, 4) is built (plain code)
+  const void* group_kernel;  // job-list kernel: __global__ void(GroupArgs), 256 threads
+  int group_vec;             // dwords per lane of its items
 
   bool has(int vec, int unroll) const {
     return (vec == 1 || vec == 2 || vec == 4) && (vec_mask & vec) &&

@@ -5,7 +5,9 @@
 //   0  the plain code (k <= p), one column slice per thread;
 //   1  the extended Q parity (p < k <= 2p-1, Section 3.3), same mapping;
 //   2  the plain code split-K: the waves of a work-group share a column tile
-//      and split the data strips.
+//      and split the data strips;
+//   3  the job-list kernel of plans: the tiles of many stripes of this prime,
+//      each with its own geometry, one per wave.
 // Each object is compiled alone so that the code of one never shapes the
 // compiler's choices for the others; object 0 holds the dispatch entry and
 // calls into the other two.
@@ -218,6 +220,30 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 }
 #endif
 
+#if RAID6C_VARIANT == 3
+// Job-list kernel of plans (plain code).  Work-groups of 4 waves; wave w of
+// work-group b takes item 4b + w: a tile of 64 lanes x GV dwords of one job
+// (any base, strip stride, row size, case), run by the same per-tile code as
+// the strided kernels.
+constexpr int kGroupVec = (kVecMask & 2) ? 2 : 1;
+
+__global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t i = blockIdx.x * 4 + w;
+  if (i >= a.nitems) return;
+  const BatchItem item = a.items[i];
+  const BatchJob& j = a.jobs[item.job];
+  const uint32_t col = item.col + lane * (kGroupVec * 4);
+  if (col >= j.row_bytes) return;
+  const ColsJob c{j.base, j.strip_stride, j.out0, j.out1, j.src, j.src_stride, j.e0, j.e1,
+                  j.row_bytes, col, (uint32_t)((kP - 1) * j.row_bytes)};
+  const Case cs{j.op, j.x, j.y};
+  tile_recover<kP, kGroupVec, 1, false>(c, j.k, cs, smem + threadIdx.x, 256);
+}
+#endif
+
 // (vec, unroll) pairs built for this prime: accumulators take (2p-1)*vec
 // dwords per thread and a batch of loads unroll*(p-1)*vec more.
 template <int V, int U>
@@ -242,7 +268,7 @@ constexpr int unroll_mask(int v) {
 template <int V, int U>
 hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                      hipStream_t stream) {
-  if constexpr (built<V, U>()) {
+  if constexpr (built<V, U>() && RAID6C_VARIANT != 3) {
 #if RAID6C_VARIANT == 2
     (void)kind;
     if (a.k > kP) return hipErrorInvalidValue;
@@ -291,13 +317,18 @@ hipError_t launch_here(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32
 
 }  // namespace
 
-// Launchers of the other two objects of this prime.
+// Launchers of the other objects of this prime.
 hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                                                 hipStream_t stream);
 hipError_t RAID6C_CAT(zp_launch_split_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                                                   hipStream_t stream);
+const void* RAID6C_CAT(zp_group_kernel_, RAID6C_P)();
+int RAID6C_CAT(zp_group_vec_, RAID6C_P)();
 
-#if RAID6C_VARIANT == 1
+#if RAID6C_VARIANT == 3
+const void* RAID6C_CAT(zp_group_kernel_, RAID6C_P)() { return (const void*)zp_group_kernel; }
+int RAID6C_CAT(zp_group_vec_, RAID6C_P)() { return kGroupVec; }
+#elif RAID6C_VARIANT == 1
 hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                                                 hipStream_t stream) {
   return launch_here(kind, cfg, a, grid, stream);
@@ -319,7 +350,8 @@ hipError_t launch_plain(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint3
 const ZpPrimeEntry* RAID6C_CAT(zp_entry_, RAID6C_P)() {
   static const ZpPrimeEntry e{kP, &launch_plain, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
                               {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)},
-                              {0, split_mask(1), split_mask(2), 0, split_mask(4)}};
+                              {0, split_mask(1), split_mask(2), 0, split_mask(4)},
+                              RAID6C_CAT(zp_group_kernel_, RAID6C_P)(), RAID6C_CAT(zp_group_vec_, RAID6C_P)()};
   return &e;
 }
 #endif
