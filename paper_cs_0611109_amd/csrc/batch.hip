@@ -221,10 +221,11 @@ int build_graph(raid6c_plan* pl) {
       hipGraphNode_t node;
       void* params[] = {(void*)&pl->gargs[gi]};
       hipKernelNodeParams kp{};
-      kp.func = (void*)zp_prime_entry(g.p)->group_kernel;
-      kp.gridDim = dim3((g.n + 3) / 4);
-      kp.blockDim = dim3(256);
-      kp.sharedMemBytes = (unsigned)(g.p * 256 * 4);
+      const ZpPrimeEntry* pe = zp_prime_entry(g.p);
+      kp.func = (void*)pe->group_kernel;
+      kp.gridDim = dim3((g.n + pe->group_per_wg - 1) / pe->group_per_wg);
+      kp.blockDim = dim3(pe->group_threads);
+      kp.sharedMemBytes = (unsigned)pe->group_lds;
       kp.kernelParams = params;
       if ((e = hipGraphAddKernelNode(&node, pl->graph, nullptr, 0, &kp)) != hipSuccess)
         return fail(RAID6C_E_HIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
@@ -442,7 +443,10 @@ int raid6c_plan_stats(const raid6c_plan* plan, raid6c_plan_info* out) {
   out->user_bytes = plan->user_bytes;
   out->max_p = plan->max_p;
   uint64_t wgs = 0;
-  for (const auto& g : plan->groups) wgs += (g.n + 3) / 4;
+  for (const auto& g : plan->groups) {
+    const int per = zp_prime_entry(g.p)->group_per_wg;
+    wgs += (g.n + per - 1) / per;
+  }
   out->grid = plan->sched.grouped ? (uint32_t)wgs : (uint32_t)(plan->cus * plan->sched.waves_per_cu);
   return RAID6C_OK;
 }

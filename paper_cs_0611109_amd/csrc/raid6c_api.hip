@@ -157,6 +157,12 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
   const bool split = cfg.split > 1 && a.k <= p;
   const uint64_t tile_bytes = (uint64_t)(split ? 64 : cfg.threads) * cfg.vec * 4;
   a.tiles = (uint32_t)((a.row_bytes + tile_bytes - 1) / tile_bytes);
+  // Rows that do not all start on 128-byte lines are loaded with the
+  // ordinary cache policy (the kernels' LP parameter).
+  uint64_t addr_bits = a.stripe_stride | a.row_bytes | (uintptr_t)a.src_base | a.src_strip_stride |
+                       a.src_stripe_stride;
+  for (int j = 0; j < a.k + 2; ++j) addr_bits |= (uintptr_t)a.strip[j];
+  a.shared_lines = (addr_bits & 127u) != 0;
   // Keep grid * threads below 2^31.
   const uint64_t max_blocks = (((uint64_t)1 << 31) / cfg.threads);
   const uint64_t chunk = max_blocks / a.tiles;
@@ -168,6 +174,7 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
     if (done != 0) {
       for (int j = 0; j < a.k + 2; ++j) b.strip[j] = a.strip[j] + done * a.stripe_stride;
       if (a.erasures != nullptr) b.erasures = a.erasures + 2 * done;
+      if (a.src_base != nullptr) b.src_base = a.src_base + done * a.src_stripe_stride;
     }
     b.nstripes = (uint32_t)n;
     const ZpLauncher fn = a.k > p ? e->launch_ext : e->launch;

@@ -69,6 +69,7 @@ struct ZpArgs {
   uint64_t src_strip_stride;   // and copied to strip j; NULL = encode in place
   uint64_t src_stripe_stride;
   int32_t kind;                // ZpKind of the launch (set by the launcher)
+  int32_t shared_lines;        // some row does not start on a 128-byte line (set by the launcher)
 };
 
 // Launch configuration of a Z_p kernel.
@@ -90,7 +91,7 @@ typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs&
 struct BatchJob;
 struct BatchItem;
 // A plan's jobs of one prime run as one grid of the per-prime job-list
-// kernel (zp_kernels.hip, variant 3): work-groups of 4 waves, one item each.
+// kernel (zp_kernels.hip, variant 3).
 struct GroupArgs {
   const BatchJob* jobs;
   const BatchItem* items;    // this group's items (tiles of 64 lanes x group_vec dwords)
@@ -103,8 +104,15 @@ struct ZpPrimeEntry {
   int vec_mask;        // bit v set when vec = v is instantiated (bits 1, 2, 4)
   int unroll_mask[5];  // per vec: bit u set when (vec, unroll = u) is instantiated
   int split_mask[5];   // per vec: bit s set when split = s (2, 4) is built (plain code)
-  const void* group_kernel;  // job-list kernel: __global__ void(GroupArgs), 256 threads
-  int group_vec;             // dwords per lane of its items
+  // Job-list kernel, __global__ void(GroupArgs), and its launch shape: items
+  // are tiles of 64 lanes x group_vec dwords; a work-group of group_threads
+  // threads takes group_per_wg consecutive items (4: one per wave; 1: its
+  // waves split the strips of one item) and group_lds bytes of dynamic LDS.
+  const void* group_kernel;
+  int group_vec;
+  int group_per_wg;
+  int group_threads;
+  int group_lds;
 
   bool has(int vec, int unroll) const {
     return (vec == 1 || vec == 2 || vec == 4) && (vec_mask & vec) &&

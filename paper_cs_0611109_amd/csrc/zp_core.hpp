@@ -57,6 +57,15 @@ constexpr int kRawBufferWord3 = 0x00020000;
 #ifndef RAID6C_LOAD_POLICY
 #define RAID6C_LOAD_POLICY 2
 #endif
+// Loads of stripes whose rows do not start on 128-byte cache lines: a wave's
+// slice of a row then straddles a line that the neighbouring tile's wave
+// also reads.  Non-temporal loads let that line go before the second read
+// and it is fetched twice (up to 1.4x the bytes at 256-byte slices);
+// ordinary loads keep part of those lines for the second reader.
+#ifndef RAID6C_SHARED_LOAD_POLICY
+#define RAID6C_SHARED_LOAD_POLICY 0
+#endif
+constexpr int kLoadPolicyShared = RAID6C_SHARED_LOAD_POLICY;
 #ifndef RAID6C_STORE_POLICY
 #define RAID6C_STORE_POLICY 2
 #endif
@@ -72,8 +81,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const uint8_t* base,
 template <int V> struct bufio;
 template <> struct bufio<1> {
   typedef uint32_t T;
+  template <int LP = RAID6C_LOAD_POLICY>
   static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, RAID6C_LOAD_POLICY);
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LP);
   }
   static __device__ __forceinline__ void store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, RAID6C_STORE_POLICY);
@@ -81,8 +91,9 @@ template <> struct bufio<1> {
 };
 template <> struct bufio<2> {
   typedef vec_t<2>::type T;
+  template <int LP = RAID6C_LOAD_POLICY>
   static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, RAID6C_LOAD_POLICY);
+    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, LP);
   }
   static __device__ __forceinline__ void store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, RAID6C_STORE_POLICY);
@@ -90,8 +101,9 @@ template <> struct bufio<2> {
 };
 template <> struct bufio<4> {
   typedef vec_t<4>::type T;
+  template <int LP = RAID6C_LOAD_POLICY>
   static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, RAID6C_LOAD_POLICY);
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, LP);
   }
   // Stored as two 8-byte halves.  A buffer store of more than 8 bytes whose
   // data registers are rewritten by the very next vector ALU instructions
@@ -107,19 +119,43 @@ template <> struct bufio<4> {
   }
 };
 
+// Work-groups are handed to the 8 XCDs, each with its own L2, round-robin:
+// work-group b runs on XCD b mod 8.  xcd_chunk renumbers them so that runs
+// of RAID6C_XCD_CHUNK consecutive logical work-groups (neighbouring tiles)
+// run on one XCD at about the same time: a cache line at the edge of two
+// tiles (rows not on 128-byte lines) is then fetched into one L2, not two.
+// Full super-blocks of 8 * chunk work-groups are permuted within
+// themselves, so the load stays spread; the tail keeps its numbers.
+#ifndef RAID6C_XCD_CHUNK
+#define RAID6C_XCD_CHUNK 16
+#endif
+__device__ __forceinline__ uint32_t xcd_chunk(uint32_t b, uint32_t g) {
+#if RAID6C_XCD_CHUNK > 0
+  constexpr uint32_t C = RAID6C_XCD_CHUNK, SB = 8u * C;
+  if (b >= g / SB * SB) return b;
+  const uint32_t x = b % 8u, i = b / 8u;
+  return (i / C) * SB + x * C + i % C;
+#else
+  (void)g;
+  return b;
+#endif
+}
+
 // Where one stripe's strips are, for one thread's column slice.  Both forms
 // offer strip(j) (a buffer resource over strip j, the place the stripe's
 // strip lives and results are written), src(j) (where data strip j is read
 // from: strip(j), or a separate source when the stripe is being written from
 // a payload), copy() (true when src differs from strip, so data rows read from
 // src are also stored to strip), W() (row bytes) and col (this thread's byte
-// offset within a row).
-//  * ColsTable: a table of k+2 strip addresses (kernel argument) plus a
+// offset within a row), and kLoad, the cache policy of their loads.
+//  * ColsTableP<LP>: a table of k+2 strip addresses (kernel argument) plus a
 //    per-stripe offset; an optional source table for writes.
-//  * ColsJob: strip j at base + j * strip_stride except that the erased
+//  * ColsJobP<LP>: strip j at base + j * strip_stride except that the erased
 //    strips e0, e1 may be redirected to out0, out1 (a degraded read rebuilds
 //    them into a separate buffer); an optional contiguous source for writes.
-struct ColsTable {
+template <int LP>
+struct ColsTableP {
+  static constexpr int kLoad = LP;
   const ZpArgs* a;
   uint64_t stripe_off;   // stripe * stripe_stride
   uint64_t src_off;      // stripe * src_stripe_stride
@@ -135,8 +171,11 @@ struct ColsTable {
   }
   __device__ __forceinline__ uint64_t W() const { return a->row_bytes; }
 };
+typedef ColsTableP<RAID6C_LOAD_POLICY> ColsTable;
 
-struct ColsJob {
+template <int LP>
+struct ColsJobP {
+  static constexpr int kLoad = LP;
   uint8_t* base;
   uint64_t strip_stride;
   uint8_t* out0;         // where strip e0 is written (base + e0 * strip_stride in place)
@@ -149,7 +188,12 @@ struct ColsJob {
   uint32_t strip_bytes;
 
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t strip(int j) const {
-    uint8_t* p = j == e0 ? out0 : j == e1 ? out1 : base + (uint64_t)j * strip_stride;
+    // Two one-sided choices: a choice between the two fields out0 / out1
+    // can be compiled as one load from a computed field address, which
+    // keeps the whole object in private memory.
+    uint8_t* p = base + (uint64_t)j * strip_stride;
+    p = j == e0 ? out0 : p;
+    p = j == e1 ? out1 : p;
     return make_rsrc(p, strip_bytes);
   }
   __device__ __forceinline__ bool copy() const { return src_base != nullptr; }
@@ -158,7 +202,17 @@ struct ColsJob {
                   : make_rsrc(base + (uint64_t)j * strip_stride, strip_bytes);
   }
   __device__ __forceinline__ uint64_t W() const { return row_bytes; }
+  template <int LP2>
+  __device__ __forceinline__ ColsJobP<LP2> with_policy() const {
+    return ColsJobP<LP2>{base, strip_stride, out0, out1, src_base, src_stride, e0, e1, row_bytes, col, strip_bytes};
+  }
+  // True when every row of every strip starts on a 128-byte line.
+  __device__ __forceinline__ bool lines_aligned() const {
+    return (((uintptr_t)base | strip_stride | row_bytes | (uintptr_t)out0 | (uintptr_t)out1 |
+             (uintptr_t)src_base | src_stride) & 127u) == 0;
+  }
 };
+typedef ColsJobP<RAID6C_LOAD_POLICY> ColsJob;
 
 // Row r of a strip: the row offset r*W is the same for the whole wave and is
 // the scalar offset operand of the buffer instruction.  With
@@ -179,9 +233,9 @@ __device__ __forceinline__ uint32_t row_offset(int r, uint64_t W) {
 #endif
 }
 
-template <typename VT>
+template <typename VT, int LP = RAID6C_LOAD_POLICY>
 __device__ __forceinline__ VT ld(__amdgpu_buffer_rsrc_t s, int r, uint64_t W, uint32_t col) {
-  return bufio<sizeof(VT) / 4>::load(s, col, row_offset(r, W));
+  return bufio<sizeof(VT) / 4>::template load<LP>(s, col, row_offset(r, W));
 }
 
 template <typename VT>
@@ -227,7 +281,7 @@ __device__ __forceinline__ void stream_range(const C& c, int hi, int lo, int x, 
       } else {
         const __amdgpu_buffer_rsrc_t b = c.src(tt);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[u][r] = ld<VT>(b, r, W, c.col);
+        for (int r = 0; r < R; ++r) v[u][r] = ld<VT, C::kLoad>(b, r, W, c.col);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -260,7 +314,7 @@ __device__ __forceinline__ void stream_range(const C& c, int hi, int lo, int x, 
     const __amdgpu_buffer_rsrc_t b = c.src(t);
     VT v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = ld<VT>(b, r, W, c.col);
+    for (int r = 0; r < R; ++r) v[r] = ld<VT, C::kLoad>(b, r, W, c.col);
     __builtin_amdgcn_sched_barrier(0);
     if (c.copy()) {
       const __amdgpu_buffer_rsrc_t d = c.strip(t);
@@ -306,7 +360,7 @@ __device__ __forceinline__ void load_into(const C& c, int j, typename vec_t<V>::
   const __amdgpu_buffer_rsrc_t b = c.strip(j);
   const uint64_t W = c.W();
 #pragma unroll
-  for (int r = 0; r < P - 1; ++r) acc[r] = ld<VT>(b, r, W, c.col);
+  for (int r = 0; r < P - 1; ++r) acc[r] = ld<VT, C::kLoad>(b, r, W, c.col);
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -318,7 +372,7 @@ __device__ __forceinline__ void xor_from(const C& c, int j, typename vec_t<V>::t
   const uint64_t W = c.W();
   VT v[P - 1];
 #pragma unroll
-  for (int r = 0; r < P - 1; ++r) v[r] = ld<VT>(b, r, W, c.col);
+  for (int r = 0; r < P - 1; ++r) v[r] = ld<VT, C::kLoad>(b, r, W, c.col);
   // All rows in flight before the first use (as in the streaming phase).
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -690,6 +744,128 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
     with_p(cs.y);
     xor_from<P, V>(c, iQ, aq);
     finish_recover<P, V, EXT>(c, k, Case{OP_DD, cs.x, cs.y}, ap, aq, lds, ls);
+  }
+}
+
+// Split-K tile (plain code).  The S waves of the work-group share one column
+// tile of 64 lanes x V dwords starting at byte `tile_base` of a row (this
+// thread's slice is c.col) and split the data strips into S contiguous
+// ranges [t0, t1); each wave runs the streaming phase on its range.  Its Q
+// partial is x^{t0} times what Horner leaves (sum_t x^{t-t0} D_t), so it goes
+// to LDS rotated by t0, next to the P partial; wave 0 (whose range starts at
+// t = 0) also adds P and/or Q where the case needs them.  After a barrier:
+//  * encode-like cases: the waves split the rows, sum the S partials and
+//    store P and the reduced Q (row r plus row p-1) V dwords per lane;
+//  * recoveries: one thread per dword column sums its column of the
+//    partials and runs finish_recover on it, with its LDS column as the
+//    permutation scratch.
+// Many waves on one stripe at a time keeps fewer stripes in flight, which
+// the memory system rewards.  `part` holds S*(2p-1)*64*V dwords; the case
+// must be uniform over the work-group and every thread must call this.
+template <int P, int V, int U, int S, class C>
+__device__ __forceinline__ void tile_split(const C& c, int k, const Case& cs_in, uint32_t tile_base,
+                                           uint32_t* part) {
+  typedef typename vec_t<V>::type VT;
+  typedef comp<V> CP;
+  constexpr int R = P - 1;
+  constexpr int NR = 2 * P - 1;
+  constexpr int CS = 64 * V;                  // dword columns of the tile
+  const Case cs{__builtin_amdgcn_readfirstlane(cs_in.op), __builtin_amdgcn_readfirstlane(cs_in.x),
+                __builtin_amdgcn_readfirstlane(cs_in.y)};
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const uint32_t col = c.col;
+  const bool live = col < c.W();
+  // Erased data strips are skipped; P/Q are rebuilt, never read, in their cases.
+  const int x = (cs.op == OP_D || cs.op == OP_DP || cs.op == OP_DQ || cs.op == OP_DD) ? cs.x : -1;
+  const int y = cs.op == OP_DD ? cs.y : -1;
+  const bool add_p = cs.op == OP_D || cs.op == OP_DQ || cs.op == OP_DD;
+  const bool add_q = cs.op == OP_DP || cs.op == OP_DD;
+  // Balanced contiguous ranges: the strips a wave loads (surviving data
+  // strips, and for wave 0 also P and/or Q) are split evenly.  pos(m) is the
+  // first t with m surviving data strips below it.
+  const int surv = k - (x >= 0) - (y >= 0);
+  const int extra = (int)add_p + (int)add_q;
+  const int per = (surv + extra + S - 1) / S;
+  auto pos = [&](int m) {
+    int t = m;
+    if (x >= 0 && x < t) ++t;
+    if (y >= 0 && y < t) ++t;
+    return t;
+  };
+  auto clampm = [&](int m) { return m < 0 ? 0 : (m > surv ? surv : m); };
+  const int t0 = pos(clampm(w * per - extra));
+  const int t1 = pos(clampm((w + 1) * per - extra));
+  VT ap[R], aq[P];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
+#pragma unroll
+  for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
+  if (live) {
+    if (t0 < t1) stream_range<P, V, U, true, true>(c, t1 - 1, t0, x, y, ap, aq);
+    if (w == 0) {   // t0 = 0 here, so Q enters unrotated
+      if (add_p) xor_from<P, V>(c, k, ap);
+      if (add_q) xor_from<P, V>(c, k + 1, aq);
+    }
+  }
+  uint32_t* my = part + (size_t)w * NR * CS + lane * V;
+  const int rot = t0 % P;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < V; ++j) my[r * CS + j] = CP::get(ap[r], j);
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    int d = u + rot;
+    if (d >= P) d -= P;
+#pragma unroll
+    for (int j = 0; j < V; ++j) my[(R + d) * CS + j] = CP::get(aq[u], j);
+  }
+  __syncthreads();
+
+  if (cs.op == OP_PQ || cs.op == OP_P || cs.op == OP_Q) {
+    if (!live) return;
+    auto row = [&](int rr) {
+      VT v = (VT)(0u);
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          CP::set(v, j, CP::get(v, j) ^ part[((size_t)s2 * NR + rr) * CS + lane * V + j]);
+      return v;
+    };
+    const VT top = row(R + R);
+    const __amdgpu_buffer_rsrc_t bp = c.strip(k), bq = c.strip(k + 1);
+    const uint64_t W = c.W();
+    for (int r = w; r < R; r += S) {
+      if (cs.op != OP_Q) st<VT>(bp, r, W, col, row(r));
+      if (cs.op != OP_P) st<VT>(bq, r, W, col, row(R + r) ^ top);
+    }
+    return;
+  }
+
+  for (int cc = threadIdx.x; cc < CS; cc += 64 * S) {
+    const uint32_t cb = tile_base + (uint32_t)cc * 4u;
+    if (cb >= c.W()) break;
+    uint32_t fp[R], fq[P];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uint32_t v = 0u;
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) v ^= part[((size_t)s2 * NR + r) * CS + cc];
+      fp[r] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      uint32_t v = 0u;
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) v ^= part[((size_t)s2 * NR + R + u) * CS + cc];
+      fq[u] = v;
+    }
+    // Only this thread uses column cc of the partials from here on.
+    C cd = c;
+    cd.col = cb;
+    finish_recover<P, 1, false>(cd, k, cs, fp, fq, part + cc, CS);
   }
 }
 

@@ -43,23 +43,27 @@ static_assert(kP >= 3 && kP <= kMaxPrime && (kP % 2) == 1, "unsupported prime");
 // for the two accumulators, so they are only built for small p.
 constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (kP <= 31) ? (1 | 2) : 1;
 
-// EXT: k > p data strips with the extended Q parity of Section 3.3.
-template <int P, int V, int U, bool EXT>
+// EXT: k > p data strips with the extended Q parity of Section 3.3.  LP: cache
+// policy of the loads (non-temporal, or the ordinary one when rows do not all
+// start on 128-byte lines, whose edge lines two tiles read).
+template <int P, int V, int U, bool EXT, int LP>
 __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
-  const uint32_t stripe = blockIdx.x / a.tiles;
-  const uint32_t tile = blockIdx.x - stripe * a.tiles;
+  const uint32_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+  const uint32_t stripe = bid / a.tiles;
+  const uint32_t tile = bid - stripe * a.tiles;
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
-  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
-                    (uint32_t)((P - 1) * a.row_bytes)};
+  const ColsTableP<LP> c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
+                         (uint32_t)((P - 1) * a.row_bytes)};
   tile_encode<P, V, U, EXT>(c, a.k, true, true);
 }
 
-template <int P, int V, int U, bool EXT>
+template <int P, int V, int U, bool EXT, int LP>
 __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t stripe = blockIdx.x / a.tiles;
-  const uint32_t tile = blockIdx.x - stripe * a.tiles;
+  const uint32_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+  const uint32_t stripe = bid / a.tiles;
+  const uint32_t tile = bid - stripe * a.tiles;
   int e0 = a.e0, e1 = a.e1;
   if (a.erasures != nullptr) {
     // One stripe per work-group: the entry is uniform.  Saying so keeps the
@@ -74,35 +78,20 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   }
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
-  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, 0, col, (uint32_t)((P - 1) * a.row_bytes)};
+  const ColsTableP<LP> c{&a, (uint64_t)stripe * a.stripe_stride, 0, col, (uint32_t)((P - 1) * a.row_bytes)};
   uint32_t* lds = reinterpret_cast<uint32_t*>(smem) + threadIdx.x;
   tile_recover<P, V, U, EXT>(c, a.k, cs, lds, (int)blockDim.x);
 }
 
 #if RAID6C_VARIANT == 2
-// Split-K (plain code only).  The S waves of a work-group share one column
-// tile of 64 lanes x V dwords and split the data strips into S contiguous
-// ranges [t0, t1); each wave runs the streaming phase on its range.  Its Q
-// partial is x^{t0} times what Horner leaves (sum_t x^{t-t0} D_t), so it
-// goes to LDS rotated by t0, next to the P partial; wave 0 (whose range starts
-// at t = 0) also adds P and/or Q where the case needs them.  After a barrier:
-//  * encode-like cases: the waves split the rows, sum the S partials and
-//    store P and the reduced Q (row r plus row p-1) V dwords per lane;
-//  * recoveries: one thread per dword column sums its column of the
-//    partials and runs the common finishing (finish_recover) on it, with its
-//    LDS column as the permutation scratch.
-// Many waves on one stripe at a time keeps fewer stripes in flight, which
-// the memory system rewards.
-template <int P, int V, int U, int S>
+// Split-K (plain code only): the S waves of a work-group share one column
+// tile of one stripe and split its data strips (tile_split).
+template <int P, int V, int U, int S, int LP>
 __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
-  typedef typename vec_t<V>::type VT;
-  typedef comp<V> CP;
-  constexpr int R = P - 1;
-  constexpr int NR = 2 * P - 1;
-  constexpr int CS = 64 * V;                  // dword columns of the tile
-  extern __shared__ __align__(16) uint32_t part[];   // [S][NR][CS]
-  const uint32_t stripe = blockIdx.x / a.tiles;
-  const uint32_t tile = blockIdx.x - stripe * a.tiles;
+  extern __shared__ __align__(16) uint32_t part[];
+  const uint32_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+  const uint32_t stripe = bid / a.tiles;
+  const uint32_t tile = bid - stripe * a.tiles;
   Case cs{OP_PQ, -1, -1};            // an encode writes P and Q
   if (a.kind == KIND_RECOVER) {
     // Per-stripe entries, or the uniform pair of a single-stripe call.
@@ -117,106 +106,10 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
       return;
     }
   }
-  cs = Case{__builtin_amdgcn_readfirstlane(cs.op), __builtin_amdgcn_readfirstlane(cs.x),
-            __builtin_amdgcn_readfirstlane(cs.y)};
-  const int k = a.k;
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
-  const uint32_t col = (tile * 64 + lane) * (V * 4);
-  const bool live = col < a.row_bytes;
-  const uint32_t strip_bytes = (uint32_t)((P - 1) * a.row_bytes);
-  const ColsTable c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
-                    strip_bytes};
-  // Erased data strips are skipped; P/Q are rebuilt, never read, in their cases.
-  const int x = (cs.op == OP_D || cs.op == OP_DP || cs.op == OP_DQ || cs.op == OP_DD) ? cs.x : -1;
-  const int y = cs.op == OP_DD ? cs.y : -1;
-  const bool add_p = cs.op == OP_D || cs.op == OP_DQ || cs.op == OP_DD;
-  const bool add_q = cs.op == OP_DP || cs.op == OP_DD;
-  // Balanced contiguous ranges: the strips a wave loads (surviving data
-  // strips, and for wave 0 also P and/or Q) are split evenly.  pos(m) is the
-  // first t with m surviving data strips below it.
-  const int surv = k - (x >= 0) - (y >= 0);
-  const int extra = (int)add_p + (int)add_q;
-  const int per = (surv + extra + S - 1) / S;
-  auto pos = [&](int m) {
-    int t = m;
-    if (x >= 0 && x < t) ++t;
-    if (y >= 0 && y < t) ++t;
-    return t;
-  };
-  auto clampm = [&](int m) { return m < 0 ? 0 : (m > surv ? surv : m); };
-  const int t0 = pos(clampm(w * per - extra));
-  const int t1 = pos(clampm((w + 1) * per - extra));
-  VT ap[R], aq[P];
-#pragma unroll
-  for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
-#pragma unroll
-  for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
-  if (live) {
-    if (t0 < t1) stream_range<P, V, U, true, true>(c, t1 - 1, t0, x, y, ap, aq);
-    if (w == 0) {   // t0 = 0 here, so Q enters unrotated
-      if (add_p) xor_from<P, V>(c, k, ap);
-      if (add_q) xor_from<P, V>(c, k + 1, aq);
-    }
-  }
-  uint32_t* my = part + (size_t)w * NR * CS + lane * V;
-  const int rot = t0 % P;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int j = 0; j < V; ++j) my[r * CS + j] = CP::get(ap[r], j);
-#pragma unroll
-  for (int u = 0; u < P; ++u) {
-    int d = u + rot;
-    if (d >= P) d -= P;
-#pragma unroll
-    for (int j = 0; j < V; ++j) my[(R + d) * CS + j] = CP::get(aq[u], j);
-  }
-  __syncthreads();
-
-  if (cs.op == OP_PQ || cs.op == OP_P || cs.op == OP_Q) {
-    if (!live) return;
-    auto row = [&](int rr) {
-      VT v = (VT)(0u);
-#pragma unroll
-      for (int s2 = 0; s2 < S; ++s2)
-#pragma unroll
-        for (int j = 0; j < V; ++j)
-          CP::set(v, j, CP::get(v, j) ^ part[((size_t)s2 * NR + rr) * CS + lane * V + j]);
-      return v;
-    };
-    const VT top = row(R + R);
-    const __amdgpu_buffer_rsrc_t bp = c.strip(k), bq = c.strip(k + 1);
-    const uint64_t W = c.W();
-    for (int r = w; r < R; r += S) {
-      if (cs.op != OP_Q) st<VT>(bp, r, W, col, row(r));
-      if (cs.op != OP_P) st<VT>(bq, r, W, col, row(R + r) ^ top);
-    }
-    return;
-  }
-
-  for (int cc = threadIdx.x; cc < CS; cc += 64 * S) {
-    const uint32_t cb = tile * (uint32_t)(CS * 4) + (uint32_t)cc * 4u;
-    if (cb >= a.row_bytes) break;
-    uint32_t fp[R], fq[P];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      uint32_t v = 0u;
-#pragma unroll
-      for (int s2 = 0; s2 < S; ++s2) v ^= part[((size_t)s2 * NR + r) * CS + cc];
-      fp[r] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-      uint32_t v = 0u;
-#pragma unroll
-      for (int s2 = 0; s2 < S; ++s2) v ^= part[((size_t)s2 * NR + R + u) * CS + cc];
-      fq[u] = v;
-    }
-    // Only this thread uses column cc of the partials from here on.
-    const ColsTable cd{&a, (uint64_t)stripe * a.stripe_stride, 0, cb, strip_bytes};
-    finish_recover<P, 1, false>(cd, k, cs, fp, fq, part + cc, CS);
-  }
+  const uint32_t col = (tile * 64 + (threadIdx.x & 63)) * (V * 4);
+  const ColsTableP<LP> c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
+                         (uint32_t)((P - 1) * a.row_bytes)};
+  tile_split<P, V, U, S>(c, a.k, cs, tile * 64 * V * 4, part);
 }
 #endif
 
@@ -224,14 +117,22 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 // Job-list kernel of plans (plain code).  Work-groups of 4 waves; wave w of
 // work-group b takes item 4b + w: a tile of 64 lanes x GV dwords of one job
 // (any base, strip stride, row size, case), run by the same per-tile code as
-// the strided kernels.
+// the strided kernels.  Jobs whose rows are not all on 128-byte lines load
+// with the ordinary cache policy (the lines at tile edges are read by two
+// waves); the others stream non-temporally.
 constexpr int kGroupVec = (kVecMask & 2) ? 2 : 1;
+// Strips loaded per batch: two for the large primes, whose vector width is 1.
+#ifdef RAID6C_GROUP_UNROLL
+constexpr int kGroupUnroll = RAID6C_GROUP_UNROLL;
+#else
+constexpr int kGroupUnroll = kP >= 37 ? 2 : 1;
+#endif
 
 __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
   extern __shared__ __align__(16) uint32_t smem[];
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t i = blockIdx.x * 4 + w;
+  const uint32_t i = xcd_chunk(blockIdx.x, gridDim.x) * 4 + w;
   if (i >= a.nitems) return;
   const BatchItem item = a.items[i];
   const BatchJob& j = a.jobs[item.job];
@@ -240,7 +141,11 @@ __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
   const ColsJob c{j.base, j.strip_stride, j.out0, j.out1, j.src, j.src_stride, j.e0, j.e1,
                   j.row_bytes, col, (uint32_t)((kP - 1) * j.row_bytes)};
   const Case cs{j.op, j.x, j.y};
-  tile_recover<kP, kGroupVec, 1, false>(c, j.k, cs, smem + threadIdx.x, 256);
+  if (c.lines_aligned())
+    tile_recover<kP, kGroupVec, kGroupUnroll, false>(c, j.k, cs, smem + threadIdx.x, 256);
+  else
+    tile_recover<kP, kGroupVec, kGroupUnroll, false>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
+                                                     smem + threadIdx.x, 256);
 }
 #endif
 
@@ -265,8 +170,8 @@ constexpr int unroll_mask(int v) {
                 : 0;
 }
 
-template <int V, int U>
-hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+template <int V, int U, int LP>
+hipError_t launch_lp(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                      hipStream_t stream) {
   if constexpr (built<V, U>() && RAID6C_VARIANT != 3) {
 #if RAID6C_VARIANT == 2
@@ -275,13 +180,13 @@ hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t
     const dim3 g(grid);
     if constexpr ((split_mask(V) & 2) != 0) {
       if (cfg.split == 2) {
-        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 2>), g, dim3(128), sk_lds_bytes_any(V, 2), stream, a);
+        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 2, LP>), g, dim3(128), sk_lds_bytes_any(V, 2), stream, a);
         return hipGetLastError();
       }
     }
     if constexpr ((split_mask(V) & 4) != 0) {
       if (cfg.split == 4) {
-        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 4>), g, dim3(256), sk_lds_bytes_any(V, 4), stream, a);
+        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 4, LP>), g, dim3(256), sk_lds_bytes_any(V, 4), stream, a);
         return hipGetLastError();
       }
     }
@@ -290,13 +195,20 @@ hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t
     if ((a.k > kP) != kExt) return hipErrorInvalidValue;
     const dim3 g(grid), b(cfg.threads);
     const size_t lds = (size_t)kP * cfg.threads * 4;
-    if (kind == KIND_ENCODE) hipLaunchKernelGGL((zp_encode_kernel<kP, V, U, kExt>), g, b, 0, stream, a);
-    else hipLaunchKernelGGL((zp_recover_kernel<kP, V, U, kExt>), g, b, lds, stream, a);
+    if (kind == KIND_ENCODE) hipLaunchKernelGGL((zp_encode_kernel<kP, V, U, kExt, LP>), g, b, 0, stream, a);
+    else hipLaunchKernelGGL((zp_recover_kernel<kP, V, U, kExt, LP>), g, b, lds, stream, a);
     return hipGetLastError();
 #endif
   } else {
     return hipErrorInvalidValue;
   }
+}
+
+template <int V, int U>
+hipError_t launch_vu(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
+                     hipStream_t stream) {
+  if (a.shared_lines) return launch_lp<V, U, kLoadPolicyShared>(kind, cfg, a, grid, stream);
+  return launch_lp<V, U, RAID6C_LOAD_POLICY>(kind, cfg, a, grid, stream);
 }
 
 hipError_t launch_here(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
@@ -322,12 +234,16 @@ hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg
                                                 hipStream_t stream);
 hipError_t RAID6C_CAT(zp_launch_split_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                                                   hipStream_t stream);
-const void* RAID6C_CAT(zp_group_kernel_, RAID6C_P)();
-int RAID6C_CAT(zp_group_vec_, RAID6C_P)();
+void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e);
 
 #if RAID6C_VARIANT == 3
-const void* RAID6C_CAT(zp_group_kernel_, RAID6C_P)() { return (const void*)zp_group_kernel; }
-int RAID6C_CAT(zp_group_vec_, RAID6C_P)() { return kGroupVec; }
+void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e) {
+  e.group_kernel = (const void*)zp_group_kernel;
+  e.group_vec = kGroupVec;
+  e.group_per_wg = 4;
+  e.group_threads = 256;
+  e.group_lds = kP * 256 * 4;
+}
 #elif RAID6C_VARIANT == 1
 hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                                                 hipStream_t stream) {
@@ -345,13 +261,19 @@ hipError_t launch_plain(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint3
   if (cfg.split > 1) return RAID6C_CAT(zp_launch_split_, RAID6C_P)(kind, cfg, a, grid, stream);
   return launch_here(kind, cfg, a, grid, stream);
 }
+
+ZpPrimeEntry make_entry() {
+  ZpPrimeEntry e{kP, &launch_plain, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
+                 {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)},
+                 {0, split_mask(1), split_mask(2), 0, split_mask(4)},
+                 nullptr, 0, 0, 0, 0};
+  RAID6C_CAT(zp_group_shape_, RAID6C_P)(e);
+  return e;
+}
 }  // namespace
 
 const ZpPrimeEntry* RAID6C_CAT(zp_entry_, RAID6C_P)() {
-  static const ZpPrimeEntry e{kP, &launch_plain, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
-                              {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)},
-                              {0, split_mask(1), split_mask(2), 0, split_mask(4)},
-                              RAID6C_CAT(zp_group_kernel_, RAID6C_P)(), RAID6C_CAT(zp_group_vec_, RAID6C_P)()};
+  static const ZpPrimeEntry e = make_entry();
   return &e;
 }
 #endif

@@ -36,20 +36,22 @@ def _mixed_jobs(seed, n, w_max=1200):
     return out
 
 
-def _layout(specs, gap=48):
-    """Byte offsets of each stripe in one buffer, with gaps between strips."""
+def _layout(specs, gap=48, align=16):
+    """Byte offsets of each stripe in one buffer, with gaps between strips;
+    strides and stripe offsets rounded up to `align` bytes."""
+    up = lambda x: (x + align - 1) // align * align
     offs, pos = [], 0
     for (p, k, w, _) in specs:
         strip = (p - 1) * w
-        stride = strip + gap
+        stride = up(strip + gap)
         offs.append((pos, stride))
-        pos += (k + 2) * stride + 64
+        pos = up(pos + (k + 2) * stride + 64)
     return offs, pos
 
 
-def _run_plan(specs, seed, schedules=None, autotune=False):
+def _run_plan(specs, seed, schedules=None, autotune=False, align=16):
     device()
-    offs, total = _layout(specs)
+    offs, total = _layout(specs, align=align)
     raw = datagen.poison((total,), index=seed)
     want = []
     for i, ((p, k, w, e), (off, stride)) in enumerate(zip(specs, offs)):
@@ -109,6 +111,14 @@ def test_plan_every_schedule():
 def test_plan_after_autotune():
     specs = _mixed_jobs(3, 40)
     _run_plan(specs, seed=23, autotune=True)
+
+
+def test_plan_rows_on_cache_lines():
+    """Rows, strides and stripes on 128-byte lines (non-temporal loads) and,
+    in the same plan's second half, rows 16 bytes past them (ordinary loads)."""
+    specs = [(p, k, 128 * m, e) for (p, k, w, e), m in zip(_mixed_jobs(4, 40), [1, 2, 3, 5, 8] * 8)]
+    specs = [s if i < 20 else (s[0], s[1], s[2] + 16, s[3]) for i, s in enumerate(specs)]
+    _run_plan(specs, seed=25, align=128)
 
 
 def test_plan_every_case_large_prime():

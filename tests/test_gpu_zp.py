@@ -102,7 +102,8 @@ def test_recover_every_case_matches_oracle(p):
 def test_every_launch_config(p):
     for k in sorted({min(p, 6), p}):
         for (v, u, t, sp) in _configs(p):
-            for w in (16, 64 * 4 * v + 16):
+            # 128: rows on cache lines (non-temporal loads); the others not.
+            for w in (16, 128, 64 * 4 * v + 16):
                 log(f"config p={p} k={k} vec={v} unroll={u} threads={t} split={sp} W={w}")
                 r.raid6c_tune_set(p, 0, w, v, u, t, sp)
                 r.raid6c_tune_set(p, 1, w, v, u, t, sp)
