@@ -499,6 +499,18 @@ def summarize_profiles(stats_dir: str, fetch_dir: str, write_dir: str, out_dir: 
     for n, ns in avg.items():
         gbs = alg / ns
         lines.append(f"{n}: {gbs:.1f} GB/s = {gbs / HBM_PEAK_GBPS:.4f} of the 8 TB/s HBM peak")
+    # Every step launches the encode, then the recovery; when both use the
+    # same kernel the per-role figures come from the dispatch order.
+    trace = [t for t in _read_csv(os.path.join(stats_dir, "run_kernel_trace.csv"))
+             if _short_name(t["Kernel_Name"]).startswith("zp_")]
+    trace.sort(key=lambda t: int(t["Start_Timestamp"]))
+    if trace and len(trace) % 2 == 0:
+        lines += ["", "per role (source: run_kernel_trace.csv, dispatches alternate encode, recovery):"]
+        for role, sub in (("encode", trace[0::2]), ("recovery", trace[1::2])):
+            ns = [int(t["End_Timestamp"]) - int(t["Start_Timestamp"]) for t in sub]
+            mean = sum(ns) / len(ns)
+            lines.append(f"{role:<9} {_short_name(sub[0]['Kernel_Name'])}: {len(ns)} launches, avg {mean:.0f} ns, "
+                         f"{alg / mean:.1f} GB/s = {alg / mean / HBM_PEAK_GBPS:.4f} of peak")
     with open(os.path.join(out_dir, f"{WORKLOAD_TAG}_kernel_stats.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -532,6 +544,16 @@ def summarize_profiles(stats_dir: str, fetch_dir: str, write_dir: str, out_dir: 
              f"copy_1GiB WRITE_SIZE avg {cw:.0f} KiB -> write scale {ws:.4f}", ""]
     table, digest = {}, source_digest()
     import re
+
+    # The work-group order is not part of a kernel's name: take it from the
+    # configurations the profiled run used (the committed tuning cache).
+    import paper_cs_0611109_amd as r
+    from paper_cs_0611109_amd import autotune as at
+    at.load_cache()
+    orders = {}
+    for op in (0, 1):
+        v, u, t, sp, o = r.raid6c_tune_get(P, op, W)
+        orders[(v, u, t, sp)] = o
     for n in sorted(fetch):
         if n not in write:
             continue
@@ -541,7 +563,8 @@ def summarize_profiles(stats_dir: str, fetch_dir: str, write_dir: str, out_dir: 
         m = re.match(r"zp_(\w+)_kernel<(\d+), (\d+), (\d+), (\w+)(?:, \d+)?>", n)
         split = int(m.group(5)) if m.group(1) == "split" else 1
         key = n.replace(", ", ",")
-        table[key] = {"source_sha256": digest, "config": [int(m.group(3)), int(m.group(4)), wg[n], split],
+        cfg = (int(m.group(3)), int(m.group(4)), wg[n], split)
+        table[key] = {"source_sha256": digest, "config": [*cfg, orders.get(cfg, 0)],
                       "algorithmic_bytes": alg, "hbm_bytes_per_launch": hbm,
                       "fetch_kib": round(fetch[n]), "write_kib": round(write[n]),
                       "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
@@ -637,16 +660,17 @@ def main():
 
     dom = "recover" if rec_mean >= enc_mean else "encode"
     dom_ms = rec_mean if dom == "recover" else enc_mean
-    vec, unroll, threads, split = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
+    vec, unroll, threads, split, order = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
     if split > 1:
         kname = f"zp_split_kernel<{P},{vec},{unroll},{split},{LOAD_POLICY_STREAM}>"
     else:
         kname = f"zp_{dom}_kernel<{P},{vec},{unroll},false,{LOAD_POLICY_STREAM}>"
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
-    traffic = lookup_traffic(kname, (vec, unroll, threads, split), alg_bytes)
+    traffic = lookup_traffic(kname, (vec, unroll, threads, split, order), alg_bytes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": kname, "launch": {"vec": vec, "unroll": unroll, "threads": threads, "split": split},
+                "kernel": kname, "launch": {"vec": vec, "unroll": unroll, "threads": threads, "split": split,
+                                                  "order": order},
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(dom_ms, 4)}
     log(f"value {value:.1f} GB/s; encode {enc_mean:.3f} ms, recovery {rec_mean:.3f} ms per launch")
 
@@ -662,11 +686,12 @@ def main():
         "encode": {"GBps_user": round(user / (enc_mean / 1e3) / 1e9, 1),
                    "hbm_frac": round(alg_bytes / (enc_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                    "ms_p50": round(pct(enc_ms, 50), 4), "ms_p99": round(pct(enc_ms, 99), 4),
-                   "launch": dict(zip(("vec", "unroll", "threads", "split"), r.raid6c_tune_get(P, 0, W)))},
+                   "launch": dict(zip(("vec", "unroll", "threads", "split", "order"), r.raid6c_tune_get(P, 0, W)))},
         "recover_2": {"GBps_user": round(user / (rec_mean / 1e3) / 1e9, 1),
                       "hbm_frac": round(alg_bytes / (rec_mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                       "ms_p50": round(pct(rec_ms, 50), 4), "ms_p99": round(pct(rec_ms, 99), 4),
-                      "launch": dict(zip(("vec", "unroll", "threads", "split"), r.raid6c_tune_get(P, 1, W)))},
+                      "launch": dict(zip(("vec", "unroll", "threads", "split", "order"),
+                                         r.raid6c_tune_get(P, 1, W)))},
         "roofline": roofline,
         "autotune": tuned,
     }

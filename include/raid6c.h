@@ -505,15 +505,21 @@ int raid6c_unroll_mask(int p, int vec);
  * s = 2, 4); 0 when none is. */
 int raid6c_split_mask(int p, int vec);
 
-/* Record the configuration for (p, op, bucket of row_bytes).
+/* Record the configuration for (p, op, bucket of row_bytes).  order: 0 =
+ * work-groups in dispatch order, 1 = renumbered so that runs of neighbouring
+ * column tiles go to one XCD (chiplet with its own L2) together.  A launch
+ * whose rows do not all start on 128-byte lines (row_bytes, strip addresses
+ * and strides not multiples of 128) always takes order 1 and loads through
+ * the caches; otherwise loads are non-temporal.
  * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, (vec, unroll) not built
- * for p, threads not 64/128/256, or split not 1 or a built factor with
- * threads = 64*split. */
-int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split);
+ * for p, threads not 64/128/256, split not 1 or a built factor with
+ * threads = 64*split, or order not 0/1. */
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split, int order);
 
 /* The configuration a call with these arguments would use now.
  * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, or NULL outputs. */
-int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads, int* split);
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads, int* split,
+                    int* order);
 
 /* Forget every recorded configuration (back to the built-in rule). */
 void raid6c_tune_clear(void);

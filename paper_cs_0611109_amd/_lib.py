@@ -48,10 +48,10 @@ SIGNATURES = {
     "raid6c_read_degraded": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_vp), _c_int, _c_int, _vp, _vp]),
     "raid6c_vec_mask": (_c_int, [_c_int]),
     "raid6c_unroll_mask": (_c_int, [_c_int, _c_int]),
-    "raid6c_tune_set": (_c_int, [_c_int, _c_int, _c_size, _c_int, _c_int, _c_int, _c_int]),
+    "raid6c_tune_set": (_c_int, [_c_int, _c_int, _c_size, _c_int, _c_int, _c_int, _c_int, _c_int]),
     "raid6c_split_mask": (_c_int, [_c_int, _c_int]),
     "raid6c_tune_get": (_c_int, [_c_int, _c_int, _c_size, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
-                                 ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
+                                 ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "raid6c_tune_clear": (None, []),
     "raid6c_autotune_n": (_c_int, [_c_int, _c_int, _c_size, _vp, _c_size, _c_size, _c_size, _c_int, _vp, _c_int,
                                    _vp, ctypes.POINTER(ctypes.c_float)]),
@@ -303,16 +303,16 @@ def raid6c_split_mask(p: int, vec: int) -> int:
     return load().raid6c_split_mask(p, vec)
 
 
-def raid6c_tune_set(p, op, row_bytes, vec, unroll, threads, split=1):
-    return _check(load().raid6c_tune_set(p, op, row_bytes, vec, unroll, threads, split))
+def raid6c_tune_set(p, op, row_bytes, vec, unroll, threads, split=1, order=0):
+    return _check(load().raid6c_tune_set(p, op, row_bytes, vec, unroll, threads, split, order))
 
 
 def raid6c_tune_get(p, op, row_bytes):
-    """(vec, unroll, threads, split) a call with these arguments would use."""
-    v, u, t, sp = _c_int(), _c_int(), _c_int(), _c_int()
+    """(vec, unroll, threads, split, order) a call with these arguments would use."""
+    v, u, t, sp, o = _c_int(), _c_int(), _c_int(), _c_int(), _c_int()
     _check(load().raid6c_tune_get(p, op, row_bytes, ctypes.byref(v), ctypes.byref(u), ctypes.byref(t),
-                                  ctypes.byref(sp)))
-    return v.value, u.value, t.value, sp.value
+                                  ctypes.byref(sp), ctypes.byref(o)))
+    return v.value, u.value, t.value, sp.value, o.value
 
 
 def raid6c_tune_clear():

@@ -33,7 +33,7 @@ def load_cache(path: str = DEFAULT_CACHE) -> int:
     n = 0
     for e in data.get("entries", []):
         _lib.raid6c_tune_set(e["p"], e["op"], e["row_bytes"], e["vec"], e["unroll"], e["threads"],
-                             e.get("split", 1))
+                             e.get("split", 1), e.get("order", 0))
         n += 1
     return n
 
@@ -52,13 +52,13 @@ def tune(geoms, reps: int = 5, seed: int = 1):
         er = torch.from_numpy(datagen.erasures(seed, n, k, "any")).to(b.tensor.device)
         for op in (0, 1):
             ms = b.autotune(op, er if op == 1 else None, reps=reps)
-            vec, unroll, threads, split = _lib.raid6c_tune_get(p, op, w)
+            vec, unroll, threads, split, order = _lib.raid6c_tune_get(p, op, w)
             moved = (k + 2) * b.strip_stride * n
             entries.append({"p": p, "op": op, "row_bytes": w, "vec": vec, "unroll": unroll, "threads": threads,
-                            "split": split, "k": k, "nstripes": n, "ms": round(ms, 4),
+                            "split": split, "order": order, "k": k, "nstripes": n, "ms": round(ms, 4),
                             "GBps_moved": round(moved / (ms / 1e3) / 1e9, 1)})
             print(f"p={p} k={k} W={w} n={n} op={op}: vec={vec} unroll={unroll} threads={threads} split={split} "
-                  f"{ms:.4f} ms {moved / (ms / 1e3) / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+                  f"order={order} {ms:.4f} ms {moved / (ms / 1e3) / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
         del b
         torch.cuda.empty_cache()
     return entries

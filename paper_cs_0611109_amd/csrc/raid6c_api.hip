@@ -163,6 +163,7 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
                        a.src_stripe_stride;
   for (int j = 0; j < a.k + 2; ++j) addr_bits |= (uintptr_t)a.strip[j];
   a.shared_lines = (addr_bits & 127u) != 0;
+  a.xcd_order = a.shared_lines || cfg.order != 0;
   // Keep grid * threads below 2^31.
   const uint64_t max_blocks = (((uint64_t)1 << 31) / cfg.threads);
   const uint64_t chunk = max_blocks / a.tiles;
@@ -537,7 +538,7 @@ int raid6c_unroll_mask(int p, int vec) {
   return e->unroll_mask[vec];
 }
 
-int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split) {
+int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split, int order) {
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
@@ -549,23 +550,26 @@ int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int th
   if (!e->has(ZpConfig{vec, unroll, threads, split}))
     return fail(RAID6C_E_ARG, "split = %d is not built for p = %d, vec = %d with threads = %d", split, p, vec,
                 threads);
+  if (order != 0 && order != 1) return fail(RAID6C_E_ARG, "order = %d must be 0 or 1", order);
   if (row_bytes == 0) return fail(RAID6C_E_ARG, "row_bytes must be positive");
-  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads, split});
+  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads, split, order});
   return RAID6C_OK;
 }
 
-int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads, int* split) {
+int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads, int* split,
+                    int* order) {
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
   if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
-  if (vec == nullptr || unroll == nullptr || threads == nullptr || split == nullptr)
+  if (vec == nullptr || unroll == nullptr || threads == nullptr || split == nullptr || order == nullptr)
     return fail(RAID6C_E_ARG, "NULL output");
   const ZpConfig c = choose_config(*e, (ZpKind)op, row_bytes);
   *vec = c.vec;
   *unroll = c.unroll;
   *threads = c.threads;
   *split = c.split;
+  *order = c.order;
   return RAID6C_OK;
 }
 
@@ -618,22 +622,37 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
         for (int sp = 2; sp <= 4; sp *= 2)
           if (e->split_mask[vec] & sp) cands[ncand++] = ZpConfig{vec, unroll, 64 * sp, sp};
     }
-  for (int ci = 0; ci < ncand && rc == RAID6C_OK; ++ci) {
-    const ZpConfig cfg = cands[ci];
+  // Mean time per launch of one configuration (after one warm-up launch).
+  auto time_cfg = [&](const ZpConfig& cfg, float* ms) {
     set_tuned(p, kind, bucket, cfg);
-    if ((rc = launch_zp(p, kind, a, nstripes, stream)) != RAID6C_OK) break;
+    int r2 = launch_zp(p, kind, a, nstripes, stream);
+    if (r2 != RAID6C_OK) return r2;
     (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps && rc == RAID6C_OK; ++r) rc = launch_zp(p, kind, a, nstripes, stream);
+    for (int r = 0; r < reps && r2 == RAID6C_OK; ++r) r2 = launch_zp(p, kind, a, nstripes, stream);
     (void)hipEventRecord(e1, s);
-    if (rc != RAID6C_OK) break;
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      rc = fail(RAID6C_E_HIP, "hipEventSynchronize failed");
-      break;
+    if (r2 != RAID6C_OK) return r2;
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(RAID6C_E_HIP, "hipEventSynchronize failed");
+    (void)hipEventElapsedTime(ms, e0, e1);
+    *ms /= (float)reps;
+    return RAID6C_OK;
+  };
+  float times[9 * 5];
+  for (int ci = 0; ci < ncand && rc == RAID6C_OK; ++ci) {
+    rc = time_cfg(cands[ci], &times[ci]);
+    if (rc == RAID6C_OK && times[ci] < best_t) {
+      best_t = times[ci];
+      best = cands[ci];
     }
+  }
+  // The XCD-chunked work-group order for the configurations within 5% of
+  // the best.
+  for (int ci = 0; ci < ncand && rc == RAID6C_OK; ++ci) {
+    if (times[ci] > 1.05f * best_t) continue;
+    ZpConfig cfg = cands[ci];
+    cfg.order = 1;
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    ms /= (float)reps;
-    if (ms < best_t) {
+    rc = time_cfg(cfg, &ms);
+    if (rc == RAID6C_OK && ms < best_t) {
       best_t = ms;
       best = cfg;
     }

@@ -10,7 +10,7 @@ namespace raid6c {
 namespace {
 
 constexpr int kBuckets = 31;
-// Packed (split << 20 | vec << 16 | unroll << 12 | threads), 0 = no entry;
+// Packed (order << 24 | split << 20 | vec << 16 | unroll << 12 | threads), 0 = no entry;
 // [p][kind][bucket].
 std::atomic<uint32_t> g_table[kMaxPrime + 1][2][kBuckets];
 
@@ -22,11 +22,13 @@ int env_int(const char* name) {
 bool valid(const ZpPrimeEntry& e, const ZpConfig& c) { return e.has(c); }
 
 uint32_t pack(const ZpConfig& c) {
-  return ((uint32_t)c.split << 20) | ((uint32_t)c.vec << 16) | ((uint32_t)c.unroll << 12) | (uint32_t)c.threads;
+  return ((uint32_t)c.order << 24) | ((uint32_t)c.split << 20) | ((uint32_t)c.vec << 16) |
+         ((uint32_t)c.unroll << 12) | (uint32_t)c.threads;
 }
 
 ZpConfig unpack(uint32_t t) {
-  return ZpConfig{(int)((t >> 16) & 0xF), (int)((t >> 12) & 0xF), (int)(t & 0xFFF), (int)((t >> 20) & 0xF)};
+  return ZpConfig{(int)((t >> 16) & 0xF), (int)((t >> 12) & 0xF), (int)(t & 0xFFF), (int)((t >> 20) & 0xF),
+                  (int)((t >> 24) & 0xF)};
 }
 
 }  // namespace
@@ -90,8 +92,9 @@ ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) {
   static const int env_unroll = env_int("RAID6C_ZP_UNROLL");
   static const int env_threads = env_int("RAID6C_ZP_THREADS");
   static const int env_split = env_int("RAID6C_ZP_SPLIT");
+  static const int env_order = env_int("RAID6C_ZP_ORDER");
   if (env_vec != 0 && env_threads != 0) {
-    const ZpConfig c{env_vec, env_unroll ? env_unroll : 1, env_threads, env_split ? env_split : 1};
+    const ZpConfig c{env_vec, env_unroll ? env_unroll : 1, env_threads, env_split ? env_split : 1, env_order};
     if (valid(e, c)) return c;
   }
   const uint32_t t = g_table[e.p][kind][row_bucket(row_bytes)].load();

@@ -45,10 +45,12 @@ constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (kP <= 31) ? (1 | 2) : 1;
 
 // EXT: k > p data strips with the extended Q parity of Section 3.3.  LP: cache
 // policy of the loads (non-temporal, or the ordinary one when rows do not all
-// start on 128-byte lines, whose edge lines two tiles read).
+// start on 128-byte lines, whose edge lines two tiles read).  The work-group
+// order (dispatch order, or XCD-chunked: xcd_chunk) is a launch parameter;
+// launches whose rows are off the lines always take the chunked one.
 template <int P, int V, int U, bool EXT, int LP>
 __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
-  const uint32_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+  const uint32_t bid = a.xcd_order ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
   const uint32_t stripe = bid / a.tiles;
   const uint32_t tile = bid - stripe * a.tiles;
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
@@ -61,7 +63,7 @@ __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
 template <int P, int V, int U, bool EXT, int LP>
 __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+  const uint32_t bid = a.xcd_order ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
   const uint32_t stripe = bid / a.tiles;
   const uint32_t tile = bid - stripe * a.tiles;
   int e0 = a.e0, e1 = a.e1;
@@ -89,7 +91,7 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
 template <int P, int V, int U, int S, int LP>
 __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint32_t part[];
-  const uint32_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+  const uint32_t bid = a.xcd_order ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
   const uint32_t stripe = bid / a.tiles;
   const uint32_t tile = bid - stripe * a.tiles;
   Case cs{OP_PQ, -1, -1};            // an encode writes P and Q

@@ -155,12 +155,13 @@ def test_tuning_table():
     r.raid6c_tune_clear()
     d0 = r.raid6c_tune_get(13, 0, 4096)
     assert d0[0] in (1, 2, 4) and d0[1] in (1, 2, 4) and d0[2] in (64, 128, 256) and d0[3] in (1, 2, 4)
+    assert d0[4] in (0, 1)
     r.raid6c_tune_set(13, 0, 4096, 1, 2, 128)
-    assert r.raid6c_tune_get(13, 0, 4096) == (1, 2, 128, 1)
-    assert r.raid6c_tune_get(13, 0, 4096 + 2048) == (1, 2, 128, 1)     # same power-of-two bucket
-    assert r.raid6c_tune_get(13, 0, 8192) == d0 or r.raid6c_tune_get(13, 0, 8192) != (1, 2, 128, 1)
-    r.raid6c_tune_set(13, 1, 4096, 2, 1, 256, 4)
-    assert r.raid6c_tune_get(13, 1, 4096) == (2, 1, 256, 4)
+    assert r.raid6c_tune_get(13, 0, 4096) == (1, 2, 128, 1, 0)
+    assert r.raid6c_tune_get(13, 0, 4096 + 2048) == (1, 2, 128, 1, 0)     # same power-of-two bucket
+    assert r.raid6c_tune_get(13, 0, 8192) == d0 or r.raid6c_tune_get(13, 0, 8192) != (1, 2, 128, 1, 0)
+    r.raid6c_tune_set(13, 1, 4096, 2, 1, 256, 4, 1)
+    assert r.raid6c_tune_get(13, 1, 4096) == (2, 1, 256, 4, 1)
     r.raid6c_tune_clear()
     assert r.raid6c_tune_get(13, 0, 4096) == d0
     _err(r.raid6c_tune_set, 9, 0, 64, 1, 1, 64)
@@ -172,6 +173,7 @@ def test_tuning_table():
     _err(r.raid6c_tune_set, 13, 0, 64, 2, 1, 128, 4)   # split 4 needs 256 threads
     _err(r.raid6c_tune_set, 13, 0, 64, 2, 1, 256, 3)   # no split 3
     _err(r.raid6c_tune_set, 61, 0, 64, 1, 1, 256, 4)   # partials of 4 waves exceed 64 KiB of LDS at p = 61
+    _err(r.raid6c_tune_set, 13, 0, 64, 1, 1, 64, 1, 2)  # order 0 or 1
 
 
 def test_built_configurations():
@@ -188,7 +190,8 @@ def test_built_configurations():
             for sp in (2, 4):
                 fits = sp * (2 * p - 1) * 64 * v * 4 <= 65536
                 assert bool(r.raid6c_split_mask(p, v) & sp) == (fits and m != 0), (p, v, sp)
-        v, u, t, sp = r.raid6c_tune_get(p, 1, 1024)
+        v, u, t, sp, order = r.raid6c_tune_get(p, 1, 1024)
+        assert order in (0, 1)
         assert r.raid6c_unroll_mask(p, v) & u
         assert sp == 1 or (r.raid6c_split_mask(p, v) & sp and t == 64 * sp)
 

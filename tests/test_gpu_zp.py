@@ -101,12 +101,14 @@ def test_recover_every_case_matches_oracle(p):
 @pytest.mark.parametrize("p", [3, 5, 7, 11, 13, 17, 29, 31, 37, 61])
 def test_every_launch_config(p):
     for k in sorted({min(p, 6), p}):
-        for (v, u, t, sp) in _configs(p):
-            # 128: rows on cache lines (non-temporal loads); the others not.
+        for ci, (v, u, t, sp) in enumerate(_configs(p)):
+            # 128: rows on cache lines (non-temporal loads, work-group order
+            # as configured: alternating); the others not (chunked order).
+            order = ci % 2
             for w in (16, 128, 64 * 4 * v + 16):
-                log(f"config p={p} k={k} vec={v} unroll={u} threads={t} split={sp} W={w}")
-                r.raid6c_tune_set(p, 0, w, v, u, t, sp)
-                r.raid6c_tune_set(p, 1, w, v, u, t, sp)
+                log(f"config p={p} k={k} vec={v} unroll={u} threads={t} split={sp} order={order} W={w}")
+                r.raid6c_tune_set(p, 0, w, v, u, t, sp, order)
+                r.raid6c_tune_set(p, 1, w, v, u, t, sp, order)
                 want = _stripes(p, k, w, 4, seed=7 * p + v + t + u)
                 assert np.array_equal(_encode_on_gpu(want, p, k, w), want), (v, u, t, sp, w)
                 er = datagen.erasures(v * 1000 + t + u, 4, k, "any")
