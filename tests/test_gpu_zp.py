@@ -259,13 +259,35 @@ def test_every_config_every_two_erasure_kind_many_stripes(p, w):
     k = p - 1
     n = 192
     want = zp.encode_stripe(datagen.fill_stripes(p, 0, n, k, p, w), p)
-    for (v, u, t, sp) in _configs(p):
-        r.raid6c_tune_set(p, 0, w, v, u, t, sp)
-        r.raid6c_tune_set(p, 1, w, v, u, t, sp)
-        log(f"many stripes p={p} W={w} vec={v} unroll={u} threads={t} split={sp}")
+    for ci, (v, u, t, sp) in enumerate(_configs(p)):
+        order = ci % 2                  # both work-group orders; grids of 10^3 work-groups
+        r.raid6c_tune_set(p, 0, w, v, u, t, sp, order)
+        r.raid6c_tune_set(p, 1, w, v, u, t, sp, order)
+        log(f"many stripes p={p} W={w} vec={v} unroll={u} threads={t} split={sp} order={order}")
         assert np.array_equal(_encode_on_gpu(want, p, k, w), want), ("encode", v, u, t, sp)
         for kind in ("dd", "dp", "dq", "pq", "d"):
             er = datagen.erasures(p * 100 + v + u + t, n, k, kind)
             got = _recover_on_gpu(want, p, k, w, er)
             bad = [s for s in range(n) if not np.array_equal(got[s], want[s])]
             assert not bad, (kind, v, u, t, sp, bad[:5], [tuple(er[s]) for s in bad[:5]])
+
+
+@pytest.mark.parametrize("p,k,w,n", [(13, 12, 4112, 250), (53, 6, 2064, 200)])
+def test_rows_off_lines_many_work_groups(p, k, w, n):
+    # Rows 16 bytes past a 128-byte multiple: every launch loads through the
+    # caches and takes the XCD-chunked work-group order, which permutes full
+    # super-blocks of 128 work-groups and leaves the tail in place.  These
+    # grids hold several super-blocks and a tail in every configuration.
+    want = zp.encode_stripe(datagen.fill_stripes(p + 1, 0, n, k, p, w), p)
+    for (v, u, t, sp) in _configs(p):
+        tile = (64 if sp > 1 else t) * v * 4
+        grid = n * -(-w // tile)
+        assert grid > 2 * 128 and grid % 128 != 0, (v, t, sp, grid)
+        r.raid6c_tune_set(p, 0, w, v, u, t, sp)
+        r.raid6c_tune_set(p, 1, w, v, u, t, sp)
+        log(f"rows off lines p={p} k={k} W={w} vec={v} unroll={u} threads={t} split={sp} grid={grid}")
+        assert np.array_equal(_encode_on_gpu(want, p, k, w), want), ("encode", v, u, t, sp)
+        er = datagen.erasures(p * 7 + v + u + t, n, k, "any")
+        got = _recover_on_gpu(want, p, k, w, er)
+        bad = [s for s in range(n) if not np.array_equal(got[s], want[s])]
+        assert not bad, (v, u, t, sp, bad[:5])
