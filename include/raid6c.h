@@ -375,7 +375,8 @@ int raid6c_run_jobs(const raid6c_job* jobs, size_t njobs, void* stream);
  * the oldest stripes that no admitted request is using, and waits while the
  * oldest one is busy.  A scheduler thread admits pending requests into free
  * slots (up to max_inflight batches on their own streams, max_batch requests
- * each) and launches each batch as one persistent kernel; requests arriving
+ * each) and launches each batch as one job-list grid per prime (or one
+ * persistent kernel, `persistent`); requests arriving
  * meanwhile go into the next free slot, so batches overlap on the device.  A
  * completion thread reports each request with its arrival, launch and
  * completion times (ns on the server's steady clock).  With `plain` set,
@@ -427,6 +428,8 @@ typedef struct raid6c_server_config {
   int32_t max_batch;     /* requests per batch, 1..65536 */
   int32_t plain;         /* 1: one plain launch per request on one stream */
   int32_t waves_per_cu;  /* persistent work-groups per compute unit (0 = 8) */
+  int32_t persistent;    /* 0: a batch is one grid of the job-list kernel per prime present
+                            (as a plan's grouped schedule); 1: one persistent kernel */
 } raid6c_server_config;
 
 typedef struct raid6c_server_stats {

@@ -104,7 +104,7 @@ class raid6c_completion(ctypes.Structure):
 
 class raid6c_server_config(ctypes.Structure):
     _fields_ = [("store_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("plain", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+                ("plain", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class raid6c_server_stats(ctypes.Structure):
@@ -146,6 +146,11 @@ def load(path: str = LIB_PATH):
         raise ImportError(
             f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
             "or `python paper_cs_0611109_amd/build.py`")
+    # PyTorch carries its own HIP runtime.  Loading it first makes the
+    # library bind to that same runtime (same soname), so the process has one
+    # HIP runtime and one view of the device; loaded the other way round, the
+    # library's runtime can report no device at all.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -374,8 +379,10 @@ def raid6c_autotune_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstrip
     return ms.value
 
 
-def raid6c_server_create(store_bytes, max_inflight=4, max_batch=256, plain=False, waves_per_cu=0) -> int:
-    cfg = raid6c_server_config(store_bytes, max_inflight, max_batch, 1 if plain else 0, waves_per_cu)
+def raid6c_server_create(store_bytes, max_inflight=4, max_batch=256, plain=False, waves_per_cu=0,
+                         persistent=False) -> int:
+    cfg = raid6c_server_config(store_bytes, max_inflight, max_batch, 1 if plain else 0, waves_per_cu,
+                               1 if persistent else 0)
     out = _vp()
     _check(load().raid6c_server_create(ctypes.byref(cfg), ctypes.byref(out)))
     return out.value

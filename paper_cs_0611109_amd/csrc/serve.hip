@@ -8,8 +8,9 @@
 // are evicted when a write needs room.
 //
 // A scheduler thread admits pending requests into free "slots" (a stream, an
-// event and job/item tables) and launches each slot's requests as one
-// persistent kernel (the plan kernel of batch.hip); requests that arrive
+// event and job/item tables) and launches each slot's requests as one grid
+// of the job-list kernel per prime present (a plan's grouped schedule), or,
+// with `persistent` set, as one persistent kernel (batch.hip); requests that arrive
 // while slots are busy are admitted into the next free slot, so up to
 // max_inflight batches overlap on the device.  A completion thread polls the
 // slots' events, stamps completion times and releases stripes.  With
@@ -29,6 +30,7 @@
 #include <new>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/raid6c.h"
@@ -53,6 +55,12 @@ bool is_odd_prime(int p) {
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+struct Pending {
+  raid6c_request req;
+  uint64_t arrival_ns;
+  size_t index;    // position in a replay, else SIZE_MAX
+};
+
 struct Resident {
   uint64_t id;
   uint64_t off;    // byte offset in the store
@@ -62,12 +70,7 @@ struct Resident {
   int refs;        // admitted requests not yet complete
   bool ready;      // its write has completed
   bool evicted;
-};
-
-struct Pending {
-  raid6c_request req;
-  uint64_t arrival_ns;
-  size_t index;    // position in a replay, else SIZE_MAX
+  std::vector<Pending> waiters;  // reads that arrived before the write completed
 };
 
 struct InFlight {
@@ -88,6 +91,7 @@ struct Slot {
   uint64_t launch_ns = 0;
   bool busy = false;      // owns requests
   bool launched = false;  // its completion event has been recorded
+  std::vector<uint8_t*> retired_h, retired_d;  // outgrown tables, freed at destroy
 };
 
 }  // namespace
@@ -110,6 +114,7 @@ struct raid6c_server {
   std::deque<raid6c_completion> done;
   raid6c_completion* replay_out = nullptr;
   size_t outstanding = 0;            // submitted, not complete
+  size_t parked = 0;                 // reads waiting in a stripe's waiters
   bool stopping = false;
   raid6c_server_stats stats{};
   Clock::time_point t0 = Clock::now();
@@ -193,13 +198,15 @@ size_t table_bytes(size_t jobs, size_t items) {
 }
 
 // Make room for a batch's tables; a new device block starts with a zeroed
-// counter.  Called without the lock, on the slot's stream being idle.
+// counter.  Called without the lock, on the slot's stream being idle.  The
+// outgrown buffers are kept until the server is destroyed: freeing them now
+// would synchronise the whole device and stall every batch in flight.
 bool grow_slot(Slot& sl, size_t jobs, size_t items) {
   const size_t need = table_bytes(jobs, items);
   if (need <= sl.cap) return true;
   const size_t cap = std::max(need, sl.cap * 2 + 65536);
-  if (sl.h_buf) (void)hipHostFree(sl.h_buf);
-  if (sl.d_mem) (void)hipFree(sl.d_mem);
+  if (sl.h_buf) sl.retired_h.push_back(sl.h_buf);
+  if (sl.d_mem) sl.retired_d.push_back(sl.d_mem);
   sl.h_buf = nullptr;
   sl.d_mem = nullptr;
   sl.cap = 0;
@@ -209,6 +216,36 @@ bool grow_slot(Slot& sl, size_t jobs, size_t items) {
   sl.counter = 0;
   sl.cap = cap;
   return true;
+}
+
+// The plan job of one admitted request.
+void fill_job(const raid6c_server* s, const InFlight& f, BatchJob& j) {
+  const Resident* st = f.stripe;
+  const size_t strip = (size_t)(st->p - 1) * st->row_bytes;
+  memset(&j, 0, sizeof j);
+  j.base = s->store + st->off;
+  j.strip_stride = strip;
+  j.row_bytes = st->row_bytes;
+  j.p = (int16_t)st->p;
+  j.k = (int16_t)st->k;
+  j.e0 = j.e1 = -1;
+  if (f.req.kind == RAID6C_REQ_WRITE) {
+    j.op = OP_PQ;
+    j.x = j.y = -1;
+    j.src = (const uint8_t*)f.req.src;
+    j.src_stride = strip;
+  } else {
+    const Case cs = classify(st->k, f.req.e0, f.req.e1);
+    j.op = (int16_t)cs.op;
+    j.x = (int16_t)cs.x;
+    j.y = (int16_t)cs.y;
+    const int lo = (f.req.e1 < 0 || f.req.e0 < f.req.e1) ? f.req.e0 : f.req.e1;
+    const int hi = f.req.e1 < 0 ? -1 : (f.req.e0 < f.req.e1 ? f.req.e1 : f.req.e0);
+    j.e0 = (int16_t)lo;
+    j.out0 = (uint8_t*)f.req.dst;
+    j.e1 = (int16_t)hi;
+    j.out1 = (uint8_t*)f.req.dst + strip;
+  }
 }
 
 // Launch one slot's requests.  Called without the lock.
@@ -230,55 +267,70 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     }
     return hipEventRecord(sl.done, sl.stream);
   }
+  // h_buf: the items (column tiles), then the jobs in request order.
   size_t nitems = 0;
   for (const InFlight& f : sl.reqs) nitems += (f.stripe->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
   const size_t jobs_off = round_up(nitems * sizeof(BatchItem), 64);
   BatchItem* h_items = (BatchItem*)sl.h_buf;
   BatchJob* h_jobs = (BatchJob*)(sl.h_buf + jobs_off);
-  nitems = 0;
-  for (size_t i = 0; i < sl.reqs.size(); ++i) {
-    const InFlight& f = sl.reqs[i];
-    const Resident* st = f.stripe;
-    const size_t strip = (size_t)(st->p - 1) * st->row_bytes;
-    BatchJob& j = h_jobs[i];
-    memset(&j, 0, sizeof j);
-    j.base = s->store + st->off;
-    j.strip_stride = strip;
-    j.row_bytes = st->row_bytes;
-    j.p = (int16_t)st->p;
-    j.k = (int16_t)st->k;
-    j.e0 = j.e1 = -1;
-    if (f.req.kind == RAID6C_REQ_WRITE) {
-      j.op = OP_PQ;
-      j.x = j.y = -1;
-      j.src = (const uint8_t*)f.req.src;
-      j.src_stride = strip;
-    } else {
-      const Case cs = classify(st->k, f.req.e0, f.req.e1);
-      j.op = (int16_t)cs.op;
-      j.x = (int16_t)cs.x;
-      j.y = (int16_t)cs.y;
-      const int lo = (f.req.e1 < 0 || f.req.e0 < f.req.e1) ? f.req.e0 : f.req.e1;
-      const int hi = f.req.e1 < 0 ? -1 : (f.req.e0 < f.req.e1 ? f.req.e1 : f.req.e0);
-      j.e0 = (int16_t)lo;
-      j.out0 = (uint8_t*)f.req.dst;
-      j.e1 = (int16_t)hi;
-      j.out1 = (uint8_t*)f.req.dst + strip;
-    }
-    for (uint32_t c = 0; c < st->row_bytes; c += kBatchTileBytes) h_items[nitems++] = BatchItem{(uint32_t)i, c};
-  }
-  // One upload for both tables.
+  for (size_t i = 0; i < sl.reqs.size(); ++i) fill_job(s, sl.reqs[i], h_jobs[i]);
   uint64_t* d_counter = (uint64_t*)sl.d_mem;
   uint8_t* d_tab = sl.d_mem + 256;
-  hipError_t e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob),
-                                hipMemcpyHostToDevice, sl.stream);
+  const BatchJob* d_jobs = (const BatchJob*)(d_tab + jobs_off);
+  const BatchItem* d_items = (const BatchItem*)d_tab;
+  hipError_t e;
+  if (!s->cfg.persistent) {
+    // One grid of each prime's job-list kernel (as in a plan's grouped
+    // schedule): requests by prime, largest first; items are that prime's
+    // tiles (at least kBatchTileBytes, so the table holds them).
+    std::vector<uint32_t> order(sl.reqs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return sl.reqs[x].stripe->p > sl.reqs[y].stripe->p; });
+    struct Group {
+      const ZpPrimeEntry* pe;
+      uint32_t first, n;
+    };
+    std::vector<Group> groups;
+    nitems = 0;
+    for (uint32_t i : order) {
+      const Resident* st = sl.reqs[i].stripe;
+      if (groups.empty() || groups.back().pe->p != st->p)
+        groups.push_back(Group{zp_prime_entry(st->p), (uint32_t)nitems, 0});
+      const uint32_t tile = 64u * 4u * (uint32_t)groups.back().pe->group_vec;
+      for (uint32_t c = 0; c < st->row_bytes; c += tile) h_items[nitems++] = BatchItem{i, c};
+      groups.back().n = (uint32_t)nitems - groups.back().first;
+    }
+    e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice,
+                       sl.stream);
+    if (e != hipSuccess) return e;
+    for (const Group& g : groups) {
+      GroupArgs ga{d_jobs, d_items + g.first, g.n};
+      void* args[] = {(void*)&ga};
+      const int per = g.pe->group_per_wg;
+      e = hipLaunchKernel(g.pe->group_kernel, dim3((g.n + per - 1) / per), dim3(g.pe->group_threads), args,
+                          (size_t)g.pe->group_lds, sl.stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(sl.done, sl.stream);
+  }
+  // One persistent kernel over 256-byte tiles in request order.
+  nitems = 0;
+  for (size_t i = 0; i < sl.reqs.size(); ++i)
+    for (uint32_t c = 0; c < sl.reqs[i].stripe->row_bytes; c += kBatchTileBytes)
+      h_items[nitems++] = BatchItem{(uint32_t)i, c};
+  // One upload for both tables.
+  e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice,
+                     sl.stream);
   if (e != hipSuccess) return e;
   int max_p = 3;
   for (const InFlight& f : sl.reqs) max_p = std::max(max_p, f.stripe->p);
-  BatchArgs a{(const BatchJob*)(d_tab + jobs_off), (const BatchItem*)d_tab, (uint32_t)nitems, 4u, d_counter,
-              sl.counter};
   const int waves = s->cfg.waves_per_cu > 0 ? s->cfg.waves_per_cu : 8;
   int grid = s->cus * waves;
+  // Small batches: one item per pop, so that every item has a wave of its
+  // own (their tiles are latency-bound walks over the strips).
+  const uint32_t chunk = nitems <= (size_t)grid * 2 ? 1u : 4u;
+  BatchArgs a{d_jobs, d_items, (uint32_t)nitems, chunk, d_counter, sl.counter};
   const int need = (int)((nitems + a.chunk - 1) / a.chunk);
   if (need < grid) grid = std::max(1, need);
   e = batch_launch(a, grid, max_p, sl.stream);
@@ -297,26 +349,26 @@ void scheduler_loop(raid6c_server* s) {
         free_slot = &sl;
         break;
       }
-    if (s->stopping && s->pending.empty()) return;
+    if (s->stopping && s->pending.empty() && s->parked == 0) return;
     if (free_slot == nullptr || s->pending.empty()) {
       s->cv_sched.wait(lk);
       continue;
     }
-    // Admit requests in arrival order (a read of a stripe whose write is still
-    // in flight, or a write that must wait for room, is skipped this round;
-    // later requests may pass it).
+    // Admit requests in arrival order.  A read of a stripe whose write is in
+    // flight is parked on the stripe until that write completes; a write
+    // that must wait for room, and reads of it, are skipped this round.
+    // Later requests may pass either.
     Slot& sl = *free_slot;
     sl.reqs.clear();
     const size_t max_batch = s->cfg.plain ? 1 : (size_t)std::max(1, s->cfg.max_batch);
     size_t items = 0;
-    std::vector<uint64_t> waiting_writes;  // skipped writes: reads of them wait too
+    std::unordered_set<uint64_t> waiting_writes;  // skipped writes: reads of them wait too
     for (auto it = s->pending.begin(); it != s->pending.end() && sl.reqs.size() < max_batch;) {
       const raid6c_request& r = it->req;
       int status = check_request(r);
       Resident* st = nullptr;
       bool wait = false;
-      if (status == RAID6C_ST_OK && r.kind == RAID6C_REQ_READ &&
-          std::find(waiting_writes.begin(), waiting_writes.end(), r.stripe_id) != waiting_writes.end()) {
+      if (status == RAID6C_ST_OK && r.kind == RAID6C_REQ_READ && waiting_writes.count(r.stripe_id)) {
         ++it;
         continue;
       }
@@ -336,7 +388,10 @@ void scheduler_loop(raid6c_server* s) {
         } else {
           st = f->second;
           if (!st->ready) {
-            wait = true;
+            st->waiters.push_back(*it);
+            s->parked++;
+            it = s->pending.erase(it);
+            continue;
           } else if (classify(st->k, r.e0, r.e1).op == OP_BAD || r.dst == nullptr ||
                      ((uintptr_t)r.dst & 15u) != 0) {
             status = RAID6C_ST_INVALID;
@@ -345,7 +400,7 @@ void scheduler_loop(raid6c_server* s) {
         }
       }
       if (wait) {
-        if (r.kind == RAID6C_REQ_WRITE) waiting_writes.push_back(r.stripe_id);
+        if (r.kind == RAID6C_REQ_WRITE) waiting_writes.insert(r.stripe_id);
         ++it;
         continue;
       }
@@ -374,7 +429,10 @@ void scheduler_loop(raid6c_server* s) {
     sl.launch_ns = s->now_ns();
     if (e == hipSuccess) e = launch_slot(s, sl);
     lk.lock();
-    if (e == hipSuccess) sl.launched = true;
+    if (e == hipSuccess) {
+      sl.launched = true;
+      s->cv_done.notify_all();
+    }
     if (e != hipSuccess) {
       s->thread_error = RAID6C_E_HIP;
       // Fail the batch's requests so callers are not left waiting.
@@ -393,7 +451,7 @@ void scheduler_loop(raid6c_server* s) {
 void completer_loop(raid6c_server* s) {
   (void)hipSetDevice(s->device);
   for (;;) {
-    bool any_busy = false;
+    bool any_busy = false, progressed = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->stopping && s->outstanding == 0 && s->pending.empty()) {
@@ -412,11 +470,19 @@ void completer_loop(raid6c_server* s) {
       any_busy = true;
       const hipError_t q = hipEventQuery(sl.done);
       if (q == hipErrorNotReady) continue;
+      progressed = true;
       const uint64_t t = s->now_ns();
       std::lock_guard<std::mutex> lk(s->mu);
       const int n = (int)sl.reqs.size();
       for (const InFlight& f : sl.reqs) {
-        if (f.req.kind == RAID6C_REQ_WRITE) f.stripe->ready = true;
+        if (f.req.kind == RAID6C_REQ_WRITE) {
+          f.stripe->ready = true;
+          // Its parked reads go back to the head of the queue, oldest first.
+          std::vector<Pending>& w = f.stripe->waiters;
+          for (auto pw = w.rbegin(); pw != w.rend(); ++pw) s->pending.push_front(*pw);
+          s->parked -= w.size();
+          w.clear();
+        }
         f.stripe->refs--;
         const uint64_t user = (uint64_t)f.stripe->k * (f.stripe->p - 1) * f.stripe->row_bytes;
         complete_one(s, f.req, f.arrival_ns, f.index, q == hipSuccess ? RAID6C_ST_OK : RAID6C_ST_INVALID,
@@ -431,9 +497,10 @@ void completer_loop(raid6c_server* s) {
       s->cv_done.notify_all();
     }
     if (!any_busy) {
+      // Woken by a launch (or a stop); the timeout is a safety net.
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_done.wait_for(lk, std::chrono::microseconds(200));
-    } else {
+    } else if (!progressed) {
       std::this_thread::yield();
     }
   }
@@ -447,7 +514,8 @@ int raid6c_server_create(const raid6c_server_config* cfg, raid6c_server** out) {
   if (cfg == nullptr || out == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
   *out = nullptr;
   if (cfg->store_bytes < 4096 || cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_batch < 1 ||
-      cfg->max_batch > 65536 || cfg->waves_per_cu < 0 || cfg->waves_per_cu > 32)
+      cfg->max_batch > 65536 || cfg->waves_per_cu < 0 || cfg->waves_per_cu > 32 ||
+      (cfg->persistent != 0 && cfg->persistent != 1))
     return fail(RAID6C_E_ARG, "invalid server configuration");
   raid6c_server* s = new (std::nothrow) raid6c_server();
   if (s == nullptr) return fail(RAID6C_E_NOMEM, "out of host memory");
@@ -456,9 +524,11 @@ int raid6c_server_create(const raid6c_server_config* cfg, raid6c_server** out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) == hipSuccess && cus > 0)
     s->cus = cus;
-  if (hipMalloc((void**)&s->store, cfg->store_bytes) != hipSuccess) {
+  const hipError_t me = hipMalloc((void**)&s->store, cfg->store_bytes);
+  if (me != hipSuccess) {
     delete s;
-    return fail(RAID6C_E_NOMEM, "cannot allocate a %llu-byte stripe store", (unsigned long long)cfg->store_bytes);
+    return fail(RAID6C_E_NOMEM, "cannot allocate a %llu-byte stripe store: %s", (unsigned long long)cfg->store_bytes,
+                hipGetErrorString(me));
   }
   s->slots.resize((size_t)cfg->max_inflight);
   hipError_t e = hipSuccess;
@@ -468,6 +538,13 @@ int raid6c_server_create(const raid6c_server_config* cfg, raid6c_server** out) {
     if (cfg->plain) sl.stream = s->plain_stream;
     else e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    // Tables for max_batch requests of up to 64 column tiles each (rows up to
+    // 16 KiB), at most 4 MiB per slot; larger batches grow them.
+    if (e == hipSuccess && !cfg->plain) {
+      const size_t jobs = (size_t)cfg->max_batch;
+      const size_t items = std::min(jobs * 64, ((size_t)4 << 20) / sizeof(BatchItem));
+      if (!grow_slot(sl, jobs, items)) e = hipErrorOutOfMemory;
+    }
   }
   if (e != hipSuccess) {
     raid6c_server_destroy(s);
@@ -579,6 +656,8 @@ int raid6c_server_destroy(raid6c_server* s) {
     if (sl.stream && sl.stream != s->plain_stream) (void)hipStreamDestroy(sl.stream);
     if (sl.h_buf) (void)hipHostFree(sl.h_buf);
     if (sl.d_mem) (void)hipFree(sl.d_mem);
+    for (uint8_t* h : sl.retired_h) (void)hipHostFree(h);
+    for (uint8_t* d : sl.retired_d) (void)hipFree(d);
   }
   if (s->plain_stream) (void)hipStreamDestroy(s->plain_stream);
   for (Resident* r : s->fifo) delete r;

@@ -101,12 +101,13 @@ def _trace(seed, n, qps, pay_hi=256 << 10):
     return datagen.serve_requests(seed, n, qps, pay_hi=pay_hi)
 
 
-def test_served_results_match_oracle():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_served_results_match_oracle(persistent):
     device()
     reqs = _trace(31, 300, qps=20000.0)
     c, pay, out, out_off, data = _stage(reqs, 31)
     stripes = _expected_stripes(reqs, data)
-    srv = r.raid6c_server_create(4 << 30, max_inflight=4, max_batch=64)
+    srv = r.raid6c_server_create(4 << 30, max_inflight=4, max_batch=64, persistent=persistent)
     try:
         comps = r.raid6c_server_replay(srv, c, [q.arrival_s for q in reqs])
         st = r.raid6c_server_get_stats(srv)
@@ -122,10 +123,11 @@ def test_alone_and_in_the_mix_are_identical():
     device()
     reqs = _trace(32, 240, qps=50000.0)
     results = []
-    for plain, inflight in ((True, 8), (False, 4), (False, 1)):
+    for plain, inflight, persistent in ((True, 8, False), (False, 4, False), (False, 1, False), (False, 4, True)):
         c, pay, out, out_off, data = _stage(reqs, 32)
         stripes = _expected_stripes(reqs, data)
-        srv = r.raid6c_server_create(4 << 30, max_inflight=inflight, max_batch=32, plain=plain)
+        srv = r.raid6c_server_create(4 << 30, max_inflight=inflight, max_batch=32, plain=plain,
+                                     persistent=persistent)
         try:
             comps = r.raid6c_server_replay(srv, c, [q.arrival_s for q in reqs])
             _check(srv, reqs, comps, out, out_off, stripes)
@@ -138,11 +140,11 @@ def test_alone_and_in_the_mix_are_identical():
             results.append((to_host(out), stored, max(x.batch_size for x in comps)))
         finally:
             r.raid6c_server_destroy(srv)
-    (o0, s0, b0), (o1, s1, b1), (o2, s2, b2) = results
-    assert b0 == 1 and b1 > 1
-    assert np.array_equal(o0, o1) and np.array_equal(o0, o2)
+    (o0, s0, b0), (o1, s1, b1), (o2, s2, b2), (o3, s3, b3) = results
+    assert b0 == 1 and b1 > 1 and b3 > 1
+    assert np.array_equal(o0, o1) and np.array_equal(o0, o2) and np.array_equal(o0, o3)
     for k in s0:
-        assert np.array_equal(s0[k], s1[k]) and np.array_equal(s0[k], s2[k])
+        assert np.array_equal(s0[k], s1[k]) and np.array_equal(s0[k], s2[k]) and np.array_equal(s0[k], s3[k])
 
 
 def test_small_budget_evicts_oldest_and_reports_not_resident():
