@@ -153,10 +153,15 @@ __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
 #endif
 
 // (vec, unroll) pairs built for this prime: accumulators take (2p-1)*vec
-// dwords per thread and a batch of loads unroll*(p-1)*vec more.
+// dwords per thread and a batch of loads unroll*(p-1)*vec more.  Up to 400
+// of the 512 VGPRs a wave can hold: for the large primes four strips per
+// batch (one wave per SIMD) beat one (two or three waves) by 2-9%.
+#ifndef RAID6C_REG_BUDGET
+#define RAID6C_REG_BUDGET 400
+#endif
 template <int V, int U>
 constexpr bool built() {
-  return (kVecMask & V) != 0 && (2 * kP - 1) * V + U * (kP - 1) * V <= 192;
+  return (kVecMask & V) != 0 && (2 * kP - 1) * V + U * (kP - 1) * V <= RAID6C_REG_BUDGET;
 }
 
 // Split factors S (2, 4) built with vector width V: the partials of S

@@ -166,7 +166,7 @@ def test_tuning_table():
     assert r.raid6c_tune_get(13, 0, 4096) == d0
     _err(r.raid6c_tune_set, 9, 0, 64, 1, 1, 64)
     _err(r.raid6c_tune_set, 53, 0, 64, 4, 1, 64)     # vec 4 not built for large p
-    _err(r.raid6c_tune_set, 53, 0, 64, 1, 4, 64)     # too many registers
+    _err(r.raid6c_tune_set, 37, 0, 64, 2, 1, 64)     # vec 2 not built above p = 31
     _err(r.raid6c_tune_set, 13, 2, 64, 1, 1, 64)
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 1, 96)
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 3, 64)
@@ -186,6 +186,11 @@ def test_built_configurations():
         for v in (1, 2, 4):
             m = r.raid6c_unroll_mask(p, v)
             assert (m != 0) <= bool(r.raid6c_vec_mask(p) & v)
+            # (vec, unroll) is built when its registers ((2p-1)v accumulators and
+            # unroll*(p-1)*v loads) fit in a 400-VGPR budget
+            for u in (1, 2, 4):
+                fits = (2 * p - 1) * v + u * (p - 1) * v <= 400
+                assert bool(m & u) == (fits and bool(r.raid6c_vec_mask(p) & v)), (p, v, u)
             # split s is built exactly when s waves' partials (2p-1 rows of 64*v dwords) fit in 64 KiB
             for sp in (2, 4):
                 fits = sp * (2 * p - 1) * 64 * v * 4 <= 65536
