@@ -221,3 +221,17 @@ def test_plan_rejects_bad_jobs_before_device_work():
     _err(r.raid6c_plan_create, [J(0, 5, 6, -1, -1, 64, 256, FAKE)], code=r.RAID6C_E_UNSUPPORTED)
     # two jobs sharing bytes
     _err(r.raid6c_plan_create, [J(0, 5, 4, -1, -1, 64, 256, FAKE), J(0, 5, 4, -1, -1, 64, 256, FAKE + 1024)])
+
+
+def test_server_rejects_bad_configurations_before_device_work():
+    # Checked before the store is allocated: no device is touched.
+    _err(r.raid6c_server_create, 1024)                                   # store below 4096 bytes
+    _err(r.raid6c_server_create, 1 << 20, max_inflight=0)
+    _err(r.raid6c_server_create, 1 << 20, max_inflight=65)
+    _err(r.raid6c_server_create, 1 << 20, max_batch=0)
+    _err(r.raid6c_server_create, 1 << 20, max_batch=65537)
+    _err(r.raid6c_server_create, 1 << 20, waves_per_cu=33)
+    cfg = r.raid6c_server_config(1 << 20, 4, 64, 0, 0, 2)             # persistent must be 0 or 1
+    out = ctypes.c_void_p()
+    assert r.load().raid6c_server_create(ctypes.byref(cfg), ctypes.byref(out)) == r.RAID6C_E_ARG
+    assert not out.value and r.raid6c_last_error()
