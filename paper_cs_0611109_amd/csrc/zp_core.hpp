@@ -747,6 +747,47 @@ __device__ __forceinline__ void tile_recover(const C& c, int k, const Case& cs_i
   }
 }
 
+// Recovery of one tile with one streaming pass for every case (same
+// arguments and results as tile_recover).  The kernel then holds one copy of
+// the unrolled loop instead of one per case: the job-list kernel (two load
+// policies, every case) shrinks from 66-186 KB to 23-61 KB at the same
+// speed.  The strided kernels keep tile_recover's per-case loops, which
+// measured faster there (p = 29 double-data recovery 78% vs 72% of peak).
+//  * PQ, P, Q (re-encode): nothing erased is skipped, P and Q start at 0;
+//  * D, DQ, DD: P itself enters acc_p (plain code: first; extended: after
+//    the pass, which needs acc_p to start at zero);
+//  * DP, DD: Q itself enters acc_q after the pass.
+template <int P, int V, int U, bool EXT, class C>
+__device__ __forceinline__ void tile_recover_one_pass(const C& c, int k, const Case& cs_in, uint32_t* lds,
+                                                      int ls) {
+  typedef typename vec_t<V>::type VT;
+  constexpr int R = P - 1;
+  const int iP = k, iQ = k + 1;
+  const Case cs{__builtin_amdgcn_readfirstlane(cs_in.op), __builtin_amdgcn_readfirstlane(cs_in.x),
+                __builtin_amdgcn_readfirstlane(cs_in.y)};
+  const bool enc = cs.op == OP_PQ || cs.op == OP_P || cs.op == OP_Q;
+  const bool with_p = cs.op == OP_D || cs.op == OP_DQ || cs.op == OP_DD;
+  const bool with_q = cs.op == OP_DP || cs.op == OP_DD;
+  VT ap[R], aq[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
+  if (!EXT && with_p) {
+    load_into<P, V>(c, iP, ap);
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
+  }
+  stream_data<P, V, U, true, true, EXT>(c, k, enc ? -1 : cs.x, cs.op == OP_DD ? cs.y : -1, ap, aq);
+  if (EXT && with_p) xor_from<P, V>(c, iP, ap);
+  if (with_q) xor_from<P, V>(c, iQ, aq);
+  if (enc) {
+    if (cs.op != OP_Q) store_strip<P, V>(c, k, ap);
+    if (cs.op != OP_P) store_reduced<P, V>(c, k + 1, aq);
+    return;
+  }
+  finish_recover<P, V, EXT>(c, k, cs, ap, aq, lds, ls);
+}
+
 // Split-K tile (plain code).  The S waves of the work-group share one column
 // tile of 64 lanes x V dwords starting at byte `tile_base` of a row (this
 // thread's slice is c.col) and split the data strips into S contiguous

@@ -145,10 +145,10 @@ __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
                   j.row_bytes, col, (uint32_t)((kP - 1) * j.row_bytes)};
   const Case cs{j.op, j.x, j.y};
   if (c.lines_aligned())
-    tile_recover<kP, kGroupVec, kGroupUnroll, false>(c, j.k, cs, smem + threadIdx.x, 256);
+    tile_recover_one_pass<kP, kGroupVec, kGroupUnroll, false>(c, j.k, cs, smem + threadIdx.x, 256);
   else
-    tile_recover<kP, kGroupVec, kGroupUnroll, false>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
-                                                     smem + threadIdx.x, 256);
+    tile_recover_one_pass<kP, kGroupVec, kGroupUnroll, false>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
+                                                              smem + threadIdx.x, 256);
 }
 #endif
 
