@@ -461,6 +461,88 @@ PROFILE_CMDS = {
              "python -u bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-probe",
 }
 WORKLOAD_TAG = f"zp_p{P}_k{K}_w{W}_x{NSTRIPES}"
+# The plan workload (20,000 mixed stripes) profiled on its own: the job-list
+# kernel of each prime, grouped schedule.
+PLAN_PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_plan -o run -- "
+                    "python -u bench.py --plan-profile 10")
+PLAN_SEED, PLAN_STRIPES = 4, 20000
+
+
+def plan_jobs_bytes():
+    """Per prime: the algorithmic bytes (k+2)(p-1)W of the plan workload."""
+    import datagen
+    out = {}
+    for j in datagen.batch_jobs(PLAN_SEED, PLAN_STRIPES):
+        out[j.p] = out.get(j.p, 0) + (j.k + 2) * (j.p - 1) * j.row_bytes
+    return out
+
+
+def plan_profile(runs):
+    """Run the 20,000-stripe plan `runs` times under the grouped schedule
+    (nothing else is launched but the input fill), for the profiler."""
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    jobs = datagen.batch_jobs(PLAN_SEED, PLAN_STRIPES)
+    offs, pos = [], 0
+    for j in jobs:
+        offs.append(pos)
+        pos += (j.k + 2) * (j.p - 1) * j.row_bytes
+    buf = torch.empty(pos, dtype=torch.uint8, device="cuda:0")
+    buf.random_(0, 256)
+    base = buf.data_ptr()
+    cj = []
+    for j, off in zip(jobs, offs):
+        op = r.RAID6C_JOB_ENCODE if j.op == "encode" else r.RAID6C_JOB_RECOVER
+        cj.append(r.raid6c_job(op, j.p, j.k, j.e0, j.e1, j.row_bytes, (j.p - 1) * j.row_bytes, base + off))
+    plan = r.raid6c_plan_create((r.raid6c_job * len(cj))(*cj))
+    try:
+        r.raid6c_plan_set_schedule(plan, 8, 4, 0, 1)
+        ms = time_launches(lambda: r.raid6c_plan_run(plan), runs, torch.cuda.current_stream())
+    finally:
+        r.raid6c_plan_destroy(plan)
+    return {"plan_runs": runs, "plan_ms_mean": round(sum(ms) / len(ms), 3)}
+
+
+def summarize_plan_profile(stats_dir: str, out_dir: str = None) -> dict:
+    """Summary of a PLAN_PROFILE_CMD run (host-only): the span of each plan run
+    (first grid start to last grid end, from the kernel trace; the per-prime
+    grids overlap in time) against the algorithmic bytes, and per-prime grid
+    durations."""
+    import re
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    alg = plan_jobs_bytes()
+    total = sum(alg.values())
+    trace = [t for t in _read_csv(os.path.join(stats_dir, "run_kernel_trace.csv"))
+             if re.search(r"zp_group_kernel<\d+>", t["Kernel_Name"])]
+    trace.sort(key=lambda t: int(t["Start_Timestamp"]))
+    per_run = len(alg)
+    runs = [trace[i:i + per_run] for i in range(0, len(trace) - per_run + 1, per_run)]
+    spans = [(max(int(t["End_Timestamp"]) for t in g) - min(int(t["Start_Timestamp"]) for t in g)) for g in runs]
+    spans = spans[1:] if len(spans) > 1 else spans           # the first run warms up
+    span = sum(spans) / len(spans)
+    lines = ["# rocprofv3 kernel trace: plan of 20,000 mixed stripes (p from {5,11,13,19,29,37,53},",
+             "# k uniform in [2, p-1], rows log-uniform over 512 B..64 KiB, 60% encode / 40% two-erasure",
+             "# recovery), grouped schedule: one job-list grid per prime, the grids side by side in one graph",
+             "# command (from the repository root, on one MI355X):", "#   " + PLAN_PROFILE_CMD,
+             "# source: run_kernel_trace.csv; algorithmic bytes (k+2)(p-1)W summed over the stripes", "",
+             f"plan runs timed: {len(spans)} (after one warm-up run)",
+             f"span per run (first grid start to last grid end): {span / 1e6:.3f} ms",
+             f"algorithmic bytes per run: {total} B -> {total / span:.1f} GB/s = "
+             f"{total / span / HBM_PEAK_GBPS:.4f} of the 8 TB/s HBM peak", "",
+             "per-prime grids (they overlap in time, so a grid's duration is not its share of the run):",
+             f"{'kernel':<24}{'avg_ns':>11}{'alg_bytes':>14}"]
+    table = {"span_ns": round(span), "alg_bytes": total, "frac": round(total / span / HBM_PEAK_GBPS, 4)}
+    for p in sorted(alg, reverse=True):
+        ns = [int(t["End_Timestamp"]) - int(t["Start_Timestamp"]) for g in runs[1:] or runs for t in g
+              if f"zp_group_kernel<{p}>" in t["Kernel_Name"]]
+        avg = sum(ns) / len(ns) if ns else 0.0
+        lines.append(f"{'zp_group_kernel<%d>' % p:<24}{avg:>11.0f}{alg[p]:>14}")
+        table[p] = {"avg_ns": round(avg), "alg_bytes": alg[p]}
+    with open(os.path.join(out_dir, "zp_group_kernel_plan_mixed_x20000_kernel_stats.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return table
 
 
 def _short_name(name: str) -> str:
@@ -599,9 +681,16 @@ def main():
                     help="also run plain 1 GiB device copies (for scaling HBM byte counters)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from the three rocprofv3 runs (no GPU needed)")
+    ap.add_argument("--plan-profile", type=int, metavar="RUNS",
+                    help="only run the 20,000-stripe plan RUNS times (for the profiler)")
+    ap.add_argument("--summarize-plan", metavar="STATS_DIR",
+                    help="write the profiles/ summary of a --plan-profile run (no GPU needed)")
     args = ap.parse_args()
     if args.summarize:
         print(json.dumps(summarize_profiles(*args.summarize), indent=1))
+        return
+    if args.summarize_plan:
+        print(json.dumps(summarize_plan_profile(args.summarize_plan), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (stripes are independent, "
@@ -618,6 +707,9 @@ def main():
         sys.exit(1)
     r.load()
     stream = torch.cuda.current_stream()
+    if args.plan_profile:
+        print(json.dumps(plan_profile(args.plan_profile)), flush=True)
+        return
 
     log(f"allocating and filling p={P} k={K} W={W} x {NSTRIPES} stripes")
     batch = r.StripeBatch.empty(P, K, W, NSTRIPES)

@@ -118,8 +118,8 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 #if RAID6C_VARIANT == 3
 // Job-list kernel of plans (plain code).  Work-groups of 4 waves; wave w of
 // work-group b takes item 4b + w: a tile of 64 lanes x GV dwords of one job
-// (any base, strip stride, row size, case), run by the same per-tile code as
-// the strided kernels.  Jobs whose rows are not all on 128-byte lines load
+// (any base, strip stride, row size, case), run by tile_recover_one_pass (one
+// streaming pass for every case).  Jobs whose rows are not all on 128-byte lines load
 // with the ordinary cache policy (the lines at tile edges are read by two
 // waves); the others stream non-temporally.
 constexpr int kGroupVec = (kVecMask & 2) ? 2 : 1;
@@ -131,6 +131,8 @@ constexpr int kGroupUnroll = RAID6C_GROUP_UNROLL;
 constexpr int kGroupUnroll = 4;
 #endif
 
+// A template on P only so that profiles name each prime's grid.
+template <int P>
 __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
   extern __shared__ __align__(16) uint32_t smem[];
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -142,13 +144,13 @@ __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
   const uint32_t col = item.col + lane * (kGroupVec * 4);
   if (col >= j.row_bytes) return;
   const ColsJob c{j.base, j.strip_stride, j.out0, j.out1, j.src, j.src_stride, j.e0, j.e1,
-                  j.row_bytes, col, (uint32_t)((kP - 1) * j.row_bytes)};
+                  j.row_bytes, col, (uint32_t)((P - 1) * j.row_bytes)};
   const Case cs{j.op, j.x, j.y};
   if (c.lines_aligned())
-    tile_recover_one_pass<kP, kGroupVec, kGroupUnroll, false>(c, j.k, cs, smem + threadIdx.x, 256);
+    tile_recover_one_pass<P, kGroupVec, kGroupUnroll, false>(c, j.k, cs, smem + threadIdx.x, 256);
   else
-    tile_recover_one_pass<kP, kGroupVec, kGroupUnroll, false>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
-                                                              smem + threadIdx.x, 256);
+    tile_recover_one_pass<P, kGroupVec, kGroupUnroll, false>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
+                                                             smem + threadIdx.x, 256);
 }
 #endif
 
@@ -246,7 +248,7 @@ void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e);
 
 #if RAID6C_VARIANT == 3
 void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e) {
-  e.group_kernel = (const void*)zp_group_kernel;
+  e.group_kernel = (const void*)zp_group_kernel<kP>;
   e.group_vec = kGroupVec;
   e.group_per_wg = 4;
   e.group_threads = 256;
