@@ -488,11 +488,11 @@ int raid6c_server_destroy(raid6c_server* s);
  * 256), and `split`: 1 = every thread of the work-group owns its own column
  * slice; 2 or 4 = the work-group's `split` waves share one column tile of 64
  * lanes and split the data strips between them, combining their partial
- * sums in LDS (threads = 64*split; plain code, k <= p; an extended-parity
- * call uses the same work-group size without the split).  Only some (vec,
- * unroll) pairs and split factors are built for each prime.
+ * sums in LDS (threads = 64*split; plain code and extended Q parity alike).
+ * Only some (vec, unroll) pairs and split factors are built for each prime.
  * The library keeps one process-wide table keyed by (p, op, row-size bucket),
- * bucket = floor(log2(row_bytes)); op 0 = encode, 1 = recovery.  Entries
+ * bucket = floor(log2(row_bytes)); op 0 = encode, 1 = recovery, 2 and 3 the
+ * same for stripes with the extended Q parity (k > p).  Entries
  * change only speed, never results.
  * ------------------------------------------------------------------------ */
 
@@ -514,13 +514,13 @@ int raid6c_split_mask(int p, int vec);
  * whose rows do not all start on 128-byte lines (row_bytes, strip addresses
  * and strides not multiples of 128) always takes order 1 and loads through
  * the caches; otherwise loads are non-temporal.
- * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, (vec, unroll) not built
+ * Errors: RAID6C_E_ARG for an unbuilt p, op not 0..3, (vec, unroll) not built
  * for p, threads not 64/128/256, split not 1 or a built factor with
  * threads = 64*split, or order not 0/1. */
 int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split, int order);
 
 /* The configuration a call with these arguments would use now.
- * Errors: RAID6C_E_ARG for an unbuilt p, op not 0/1, or NULL outputs. */
+ * Errors: RAID6C_E_ARG for an unbuilt p, op not 0..3, or NULL outputs. */
 int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int* threads, int* split,
                     int* order);
 
@@ -531,7 +531,8 @@ void raid6c_tune_clear(void);
  * threads, split) configuration on the caller's stripes -- op 0: raid6c_encode_n,
  * op 1: raid6c_recover_n with `erasures` (device, as there) -- once to warm
  * up and `reps` times timed with HIP events on `stream`, then record the
- * fastest for (p, op, row-size bucket) and return its mean time per launch
+ * fastest for (p, op, row-size bucket) -- op + 2 when k > p -- and return its
+ * mean time per launch
  * in *best_ms (may be NULL).  Every run rewrites the same output bytes.
  * Synchronises.  Errors: as raid6c_encode_n / raid6c_recover_n, plus
  * RAID6C_E_ARG for op not 0/1 or reps outside 1..1000, RAID6C_E_HIP. */

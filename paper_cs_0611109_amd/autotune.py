@@ -52,12 +52,13 @@ def tune(geoms, reps: int = 5, seed: int = 1):
         er = torch.from_numpy(datagen.erasures(seed, n, k, "any")).to(b.tensor.device)
         for op in (0, 1):
             ms = b.autotune(op, er if op == 1 else None, reps=reps)
-            vec, unroll, threads, split, order = _lib.raid6c_tune_get(p, op, w)
+            slot = op + (2 if k > p else 0)        # the extended Q parity has its own entries
+            vec, unroll, threads, split, order = _lib.raid6c_tune_get(p, slot, w)
             moved = (k + 2) * b.strip_stride * n
-            entries.append({"p": p, "op": op, "row_bytes": w, "vec": vec, "unroll": unroll, "threads": threads,
+            entries.append({"p": p, "op": slot, "row_bytes": w, "vec": vec, "unroll": unroll, "threads": threads,
                             "split": split, "order": order, "k": k, "nstripes": n, "ms": round(ms, 4),
                             "GBps_moved": round(moved / (ms / 1e3) / 1e9, 1)})
-            print(f"p={p} k={k} W={w} n={n} op={op}: vec={vec} unroll={unroll} threads={threads} split={split} "
+            print(f"p={p} k={k} W={w} n={n} op={slot}: vec={vec} unroll={unroll} threads={threads} split={split} "
                   f"order={order} {ms:.4f} ms {moved / (ms / 1e3) / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
         del b
         torch.cuda.empty_cache()

@@ -151,10 +151,10 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
   if (nstripes == 0) return RAID6C_OK;
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_UNSUPPORTED, "p = %d is not built", p);
-  const ZpConfig cfg = choose_config(*e, kind, a.row_bytes);
-  // A split-K work-group covers 64 lanes x vec dwords of a row (plain code);
+  const ZpConfig cfg = choose_config(*e, tune_slot(kind, a.k > p), a.row_bytes);
+  // A split-K work-group covers 64 lanes x vec dwords of a row;
   // otherwise every thread its own vec dwords.
-  const bool split = cfg.split > 1 && a.k <= p;
+  const bool split = cfg.split > 1;
   const uint64_t tile_bytes = (uint64_t)(split ? 64 : cfg.threads) * cfg.vec * 4;
   a.tiles = (uint32_t)((a.row_bytes + tile_bytes - 1) / tile_bytes);
   // Rows that do not all start on 128-byte lines are loaded with the
@@ -178,7 +178,9 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
       if (a.src_base != nullptr) b.src_base = a.src_base + done * a.src_stripe_stride;
     }
     b.nstripes = (uint32_t)n;
-    const ZpLauncher fn = a.k > p ? e->launch_ext : e->launch;
+    // Split-K configurations (plain or extended) go through the plain entry,
+    // which hands them to the split object.
+    const ZpLauncher fn = (a.k > p && !split) ? e->launch_ext : e->launch;
     const hipError_t err = fn(kind, cfg, b, (uint32_t)(n * a.tiles), (hipStream_t)stream);
     if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     done += n;
@@ -542,7 +544,8 @@ int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int th
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
-  if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
+  if (op < 0 || op > 3)
+    return fail(RAID6C_E_ARG, "op = %d must be 0 (encode), 1 (recovery), 2 or 3 (the same, k > p)", op);
   if (!e->has(vec, unroll))
     return fail(RAID6C_E_ARG, "(vec = %d, unroll = %d) is not built for p = %d", vec, unroll, p);
   if (!(threads == 64 || threads == 128 || threads == 256))
@@ -552,7 +555,7 @@ int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int th
                 threads);
   if (order != 0 && order != 1) return fail(RAID6C_E_ARG, "order = %d must be 0 or 1", order);
   if (row_bytes == 0) return fail(RAID6C_E_ARG, "row_bytes must be positive");
-  set_tuned(p, (ZpKind)op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads, split, order});
+  set_tuned(p, op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads, split, order});
   return RAID6C_OK;
 }
 
@@ -561,10 +564,11 @@ int raid6c_tune_get(int p, int op, size_t row_bytes, int* vec, int* unroll, int*
   g_last_error.clear();
   const ZpPrimeEntry* e = zp_prime_entry(p);
   if (e == nullptr) return fail(RAID6C_E_ARG, "p = %d is not built", p);
-  if (op != 0 && op != 1) return fail(RAID6C_E_ARG, "op = %d must be 0 (encode) or 1 (recovery)", op);
+  if (op < 0 || op > 3)
+    return fail(RAID6C_E_ARG, "op = %d must be 0 (encode), 1 (recovery), 2 or 3 (the same, k > p)", op);
   if (vec == nullptr || unroll == nullptr || threads == nullptr || split == nullptr || order == nullptr)
     return fail(RAID6C_E_ARG, "NULL output");
-  const ZpConfig c = choose_config(*e, (ZpKind)op, row_bytes);
+  const ZpConfig c = choose_config(*e, op, row_bytes);
   *vec = c.vec;
   *unroll = c.unroll;
   *threads = c.threads;
@@ -604,6 +608,7 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
     return fail(RAID6C_E_HIP, "hipEventCreate failed");
   }
   const ZpKind kind = op == 0 ? KIND_ENCODE : KIND_RECOVER;
+  const int slot = tune_slot(kind, k > p);
   const int bucket = row_bucket(row_bytes);
   ZpArgs a = strided_args(k, row_bytes, base, strip_stride, stripe_stride);
   a.erasures = op == 1 ? erasures : nullptr;
@@ -611,20 +616,19 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
   float best_t = 1e30f;
   // Every built configuration: (vec, unroll) with a work-group of 64, 128 or
   // 256 threads on separate column tiles, and split-K with 2 or 4 waves on
-  // one tile (plain code only).
+  // one tile.
   ZpConfig cands[9 * 5];
   int ncand = 0;
   for (int vec = 1; vec <= 4; vec *= 2)
     for (int unroll = 1; unroll <= 4; unroll *= 2) {
       if (!e->has(vec, unroll)) continue;
       for (int threads = 64; threads <= 256; threads *= 2) cands[ncand++] = ZpConfig{vec, unroll, threads, 1};
-      if (k <= p)
-        for (int sp = 2; sp <= 4; sp *= 2)
-          if (e->split_mask[vec] & sp) cands[ncand++] = ZpConfig{vec, unroll, 64 * sp, sp};
+      for (int sp = 2; sp <= 4; sp *= 2)
+        if (e->split_mask[vec] & sp) cands[ncand++] = ZpConfig{vec, unroll, 64 * sp, sp};
     }
   // Mean time per launch of one configuration (after one warm-up launch).
   auto time_cfg = [&](const ZpConfig& cfg, float* ms) {
-    set_tuned(p, kind, bucket, cfg);
+    set_tuned(p, slot, bucket, cfg);
     int r2 = launch_zp(p, kind, a, nstripes, stream);
     if (r2 != RAID6C_OK) return r2;
     (void)hipEventRecord(e0, s);
@@ -660,7 +664,7 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != RAID6C_OK) return rc;
-  set_tuned(p, kind, bucket, best);
+  set_tuned(p, slot, bucket, best);
   if (best_ms) *best_ms = best_t;
   return RAID6C_OK;
 }

@@ -101,11 +101,11 @@ struct GroupArgs {
 };
 struct ZpPrimeEntry {
   int p;
-  ZpLauncher launch;       // plain code, k <= p (split-K configurations included)
+  ZpLauncher launch;       // plain code, k <= p, and every split-K configuration (any k)
   ZpLauncher launch_ext;   // extended Q parity, p < k <= 2p-1
   int vec_mask;        // bit v set when vec = v is instantiated (bits 1, 2, 4)
   int unroll_mask[5];  // per vec: bit u set when (vec, unroll = u) is instantiated
-  int split_mask[5];   // per vec: bit s set when split = s (2, 4) is built (plain code)
+  int split_mask[5];   // per vec: bit s set when split = s (2, 4) is built
   // Job-list kernel, __global__ void(GroupArgs), and its launch shape: items
   // are tiles of 64 lanes x group_vec dwords; a work-group of group_threads
   // threads takes group_per_wg consecutive items (4: one per wave; 1: its

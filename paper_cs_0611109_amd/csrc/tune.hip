@@ -11,8 +11,8 @@ namespace {
 
 constexpr int kBuckets = 31;
 // Packed (order << 24 | split << 20 | vec << 16 | unroll << 12 | threads), 0 = no entry;
-// [p][kind][bucket].
-std::atomic<uint32_t> g_table[kMaxPrime + 1][2][kBuckets];
+// [p][slot][bucket] (slot: tune_slot).
+std::atomic<uint32_t> g_table[kMaxPrime + 1][kTuneSlots][kBuckets];
 
 int env_int(const char* name) {
   const char* s = getenv(name);
@@ -39,9 +39,10 @@ int row_bucket(uint64_t row_bytes) {
   return b;
 }
 
-bool set_tuned(int p, ZpKind kind, int bucket, ZpConfig cfg) {
+bool set_tuned(int p, int slot, int bucket, ZpConfig cfg) {
   if (p < 3 || p > kMaxPrime || bucket < 0 || bucket >= kBuckets) return false;
-  g_table[p][kind][bucket].store(pack(cfg));
+  if (slot < 0 || slot >= kTuneSlots) return false;
+  g_table[p][slot][bucket].store(pack(cfg));
   return true;
 }
 
@@ -86,7 +87,7 @@ ZpConfig default_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) 
   return best;
 }
 
-ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) {
+ZpConfig choose_config(const ZpPrimeEntry& e, int slot, uint64_t row_bytes) {
   // Explicit override (used by tuning sweeps).
   static const int env_vec = env_int("RAID6C_ZP_VEC");
   static const int env_unroll = env_int("RAID6C_ZP_UNROLL");
@@ -97,12 +98,12 @@ ZpConfig choose_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) {
     const ZpConfig c{env_vec, env_unroll ? env_unroll : 1, env_threads, env_split ? env_split : 1, env_order};
     if (valid(e, c)) return c;
   }
-  const uint32_t t = g_table[e.p][kind][row_bucket(row_bytes)].load();
+  const uint32_t t = g_table[e.p][slot][row_bucket(row_bytes)].load();
   if (t != 0) {
     const ZpConfig c = unpack(t);
     if (valid(e, c)) return c;
   }
-  return default_config(e, kind, row_bytes);
+  return default_config(e, (ZpKind)(slot & 1), row_bytes);
 }
 
 static std::atomic<uint32_t> g_rs_override{0};  // vec<<16 | unroll<<12 | threads, 0 = none

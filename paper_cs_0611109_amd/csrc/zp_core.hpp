@@ -788,7 +788,7 @@ __device__ __forceinline__ void tile_recover_one_pass(const C& c, int k, const C
   finish_recover<P, V, EXT>(c, k, cs, ap, aq, lds, ls);
 }
 
-// Split-K tile (plain code).  The S waves of the work-group share one column
+// Split-K tile (plain code; EXT: extended Q parity, see below).  The S waves of the work-group share one column
 // tile of 64 lanes x V dwords starting at byte `tile_base` of a row (this
 // thread's slice is c.col) and split the data strips into S contiguous
 // ranges [t0, t1); each wave runs the streaming phase on its range.  Its Q
@@ -803,7 +803,7 @@ __device__ __forceinline__ void tile_recover_one_pass(const C& c, int k, const C
 // Many waves on one stripe at a time keeps fewer stripes in flight, which
 // the memory system rewards.  `part` holds S*(2p-1)*64*V dwords; the case
 // must be uniform over the work-group and every thread must call this.
-template <int P, int V, int U, int S, class C>
+template <int P, int V, int U, int S, bool EXT, class C>
 __device__ __forceinline__ void tile_split(const C& c, int k, const Case& cs_in, uint32_t tile_base,
                                            uint32_t* part) {
   typedef typename vec_t<V>::type VT;
@@ -842,8 +842,29 @@ __device__ __forceinline__ void tile_split(const C& c, int k, const Case& cs_in,
   for (int r = 0; r < R; ++r) ap[r] = (VT)(0u);
 #pragma unroll
   for (int u = 0; u < P; ++u) aq[u] = (VT)(0u);
+  // Extended Q parity (Section 3.3): in C, strip t >= p enters Q with
+  // 1 + x^{t+1}.  A range that straddles p takes the transition of
+  // stream_data at t = p: acc_q <- x acc_q + acc_p, where acc_p then holds
+  // exactly the strips >= p.  A range entirely above p multiplies its Horner
+  // sum by x once, and its plain sum (its P partial) joins the Q partial
+  // unrotated (below).
+  bool above_p = false;
   if (live) {
-    if (t0 < t1) stream_range<P, V, U, true, true>(c, t1 - 1, t0, x, y, ap, aq);
+    if (t0 < t1) {
+      if (!EXT || t1 <= P) {
+        stream_range<P, V, U, true, true>(c, t1 - 1, t0, x, y, ap, aq);
+      } else if (t0 < P) {
+        stream_range<P, V, U, true, true>(c, t1 - 1, P, x, y, ap, aq);
+        rotate_up<P>(aq);
+#pragma unroll
+        for (int r = 0; r < R; ++r) aq[r] ^= ap[r];
+        stream_range<P, V, U, true, true>(c, P - 1, t0, x, y, ap, aq);
+      } else {
+        stream_range<P, V, U, true, true>(c, t1 - 1, t0, x, y, ap, aq);
+        rotate_up<P>(aq);
+        above_p = true;
+      }
+    }
     if (w == 0) {   // t0 = 0 here, so Q enters unrotated
       if (add_p) xor_from<P, V>(c, k, ap);
       if (add_q) xor_from<P, V>(c, k + 1, aq);
@@ -861,6 +882,13 @@ __device__ __forceinline__ void tile_split(const C& c, int k, const Case& cs_in,
     if (d >= P) d -= P;
 #pragma unroll
     for (int j = 0; j < V; ++j) my[(R + d) * CS + j] = CP::get(aq[u], j);
+  }
+  if (EXT && above_p) {
+    // Only this thread touches these LDS words: no barrier needed before.
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < V; ++j) my[(R + r) * CS + j] ^= CP::get(ap[r], j);
   }
   __syncthreads();
 
@@ -906,7 +934,7 @@ __device__ __forceinline__ void tile_split(const C& c, int k, const Case& cs_in,
     // Only this thread uses column cc of the partials from here on.
     C cd = c;
     cd.col = cb;
-    finish_recover<P, 1, false>(cd, k, cs, fp, fq, part + cc, CS);
+    finish_recover<P, 1, EXT>(cd, k, cs, fp, fq, part + cc, CS);
   }
 }
 

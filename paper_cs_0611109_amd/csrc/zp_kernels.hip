@@ -4,8 +4,8 @@
 // -DRAID6C_P=<p> and -DRAID6C_VARIANT=
 //   0  the plain code (k <= p), one column slice per thread;
 //   1  the extended Q parity (p < k <= 2p-1, Section 3.3), same mapping;
-//   2  the plain code split-K: the waves of a work-group share a column tile
-//      and split the data strips;
+//   2  split-K, plain code and extended Q parity: the waves of a work-group
+//      share a column tile and split the data strips;
 //   3  the job-list kernel of plans: the tiles of many stripes of this prime,
 //      each with its own geometry, one per wave.
 // Each object is compiled alone so that the code of one never shapes the
@@ -86,9 +86,9 @@ __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
 }
 
 #if RAID6C_VARIANT == 2
-// Split-K (plain code only): the S waves of a work-group share one column
-// tile of one stripe and split its data strips (tile_split).
-template <int P, int V, int U, int S, int LP>
+// Split-K: the S waves of a work-group share one column tile of one stripe
+// and split its data strips (tile_split); EXT: extended Q parity.
+template <int P, int V, int U, int S, bool EXT, int LP>
 __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint32_t part[];
   const uint32_t bid = a.xcd_order ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
   const uint32_t col = (tile * 64 + (threadIdx.x & 63)) * (V * 4);
   const ColsTableP<LP> c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
                          (uint32_t)((P - 1) * a.row_bytes)};
-  tile_split<P, V, U, S>(c, a.k, cs, tile * 64 * V * 4, part);
+  tile_split<P, V, U, S, EXT>(c, a.k, cs, tile * 64 * V * 4, part);
 }
 #endif
 
@@ -186,17 +186,19 @@ hipError_t launch_lp(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t
   if constexpr (built<V, U>() && RAID6C_VARIANT != 3) {
 #if RAID6C_VARIANT == 2
     (void)kind;
-    if (a.k > kP) return hipErrorInvalidValue;
     const dim3 g(grid);
+    const bool ext = a.k > kP;
     if constexpr ((split_mask(V) & 2) != 0) {
       if (cfg.split == 2) {
-        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 2, LP>), g, dim3(128), sk_lds_bytes_any(V, 2), stream, a);
+        if (ext) hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 2, true, LP>), g, dim3(128), sk_lds_bytes_any(V, 2), stream, a);
+        else hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 2, false, LP>), g, dim3(128), sk_lds_bytes_any(V, 2), stream, a);
         return hipGetLastError();
       }
     }
     if constexpr ((split_mask(V) & 4) != 0) {
       if (cfg.split == 4) {
-        hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 4, LP>), g, dim3(256), sk_lds_bytes_any(V, 4), stream, a);
+        if (ext) hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 4, true, LP>), g, dim3(256), sk_lds_bytes_any(V, 4), stream, a);
+        else hipLaunchKernelGGL((zp_split_kernel<kP, V, U, 4, false, LP>), g, dim3(256), sk_lds_bytes_any(V, 4), stream, a);
         return hipGetLastError();
       }
     }
@@ -266,7 +268,7 @@ hipError_t RAID6C_CAT(zp_launch_split_, RAID6C_P)(ZpKind kind, const ZpConfig& c
 }
 #else
 namespace {
-// Plain code: split-K configurations go to the split object.
+// Plain code; split-K configurations (plain or extended) go to the split object.
 hipError_t launch_plain(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid, hipStream_t stream) {
   if (cfg.split > 1) return RAID6C_CAT(zp_launch_split_, RAID6C_P)(kind, cfg, a, grid, stream);
   return launch_here(kind, cfg, a, grid, stream);

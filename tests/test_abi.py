@@ -162,12 +162,16 @@ def test_tuning_table():
     assert r.raid6c_tune_get(13, 0, 8192) == d0 or r.raid6c_tune_get(13, 0, 8192) != (1, 2, 128, 1, 0)
     r.raid6c_tune_set(13, 1, 4096, 2, 1, 256, 4, 1)
     assert r.raid6c_tune_get(13, 1, 4096) == (2, 1, 256, 4, 1)
+    # the extended-parity slots are separate entries
+    r.raid6c_tune_set(13, 3, 4096, 1, 1, 64)
+    assert r.raid6c_tune_get(13, 3, 4096) == (1, 1, 64, 1, 0)
+    assert r.raid6c_tune_get(13, 1, 4096) == (2, 1, 256, 4, 1)
     r.raid6c_tune_clear()
     assert r.raid6c_tune_get(13, 0, 4096) == d0
     _err(r.raid6c_tune_set, 9, 0, 64, 1, 1, 64)
     _err(r.raid6c_tune_set, 53, 0, 64, 4, 1, 64)     # vec 4 not built for large p
     _err(r.raid6c_tune_set, 37, 0, 64, 2, 1, 64)     # vec 2 not built above p = 31
-    _err(r.raid6c_tune_set, 13, 2, 64, 1, 1, 64)
+    _err(r.raid6c_tune_set, 13, 4, 64, 1, 1, 64)      # op 0..3
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 1, 96)
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 3, 64)
     _err(r.raid6c_tune_set, 13, 0, 64, 2, 1, 128, 4)   # split 4 needs 256 threads

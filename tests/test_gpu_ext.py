@@ -123,8 +123,7 @@ def test_extended_every_launch_configuration(p):
         for u in (1, 2, 4):
             if not r.raid6c_unroll_mask(p, v) & u:
                 continue
-            # split-K entries apply to the plain code; an extended stripe runs
-            # them as plain work-groups of the same size
+            # split-K entries run the split-K extended kernels
             cfgs = [(t, 1) for t in (64, 128, 256)] + [(64 * sp, sp) for sp in (2, 4) if r.raid6c_split_mask(p, v) & sp]
             for t, sp in cfgs:
                 log(f"extended config p={p} k={k} vec={v} unroll={u} threads={t} split={sp}")
@@ -133,6 +132,32 @@ def test_extended_every_launch_configuration(p):
                 assert np.array_equal(_encode(want[:2], p, k, w), want[:2]), (v, u, t, sp)
                 assert np.array_equal(_recover(want, p, k, w, er), want), (v, u, t, sp)
     r.raid6c_tune_clear()
+
+
+@pytest.mark.parametrize("p", [5, 13, 29])
+def test_extended_split_every_class(p):
+    # k = 2p-1: the waves' strip ranges fall below p, straddle it, and lie
+    # wholly above it; every erasure class, every built split configuration.
+    k = 2 * p - 1
+    w = 1040 if p <= 13 else 272
+    er = _pick(p, k, 4, seed=5 * p)
+    want = _stripes(p, k, w, len(er), seed=17 * p)
+    n = 0
+    for v in (1, 2, 4):
+        for u in (1, 2, 4):
+            if not r.raid6c_unroll_mask(p, v) & u:
+                continue
+            for sp in (2, 4):
+                if not r.raid6c_split_mask(p, v) & sp:
+                    continue
+                log(f"extended split p={p} k={k} vec={v} unroll={u} split={sp} entries={len(er)}")
+                r.raid6c_tune_set(p, 0, w, v, u, 64 * sp, sp)
+                r.raid6c_tune_set(p, 1, w, v, u, 64 * sp, sp)
+                assert np.array_equal(_encode(want, p, k, w), want), (v, u, sp)
+                assert np.array_equal(_recover(want, p, k, w, er), want), (v, u, sp)
+                n += 1
+    r.raid6c_tune_clear()
+    assert n > 0
 
 
 def test_extended_single_stripe_pointer_tables():
