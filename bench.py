@@ -651,7 +651,7 @@ def summarize_profiles(stats_dir: str, fetch_dir: str, write_dir: str, out_dir: 
         hbm = int(round(fetch[n] * 1024 * fs + write[n] * 1024 * ws))
         lines.append(f"{n}: FETCH_SIZE {fetch[n]:.0f} KiB, WRITE_SIZE {write[n]:.0f} KiB per launch -> "
                      f"{hbm} B scaled HBM traffic; algorithmic {alg} B; ratio {hbm / alg:.5f}")
-        m = re.match(r"zp_(\w+)_kernel<(\d+), (\d+), (\d+), (\w+)(?:, \d+)?>", n)
+        m = re.match(r"zp_(\w+)_kernel<(\d+), (\d+), (\d+), (\w+)(?:, \w+)*>", n)
         split = int(m.group(5)) if m.group(1) == "split" else 1
         key = n.replace(", ", ",")
         cfg = (int(m.group(3)), int(m.group(4)), wg[n], split)
@@ -763,7 +763,7 @@ def main():
     dom_ms = rec_mean if dom == "recover" else enc_mean
     vec, unroll, threads, split, order = r.raid6c_tune_get(P, 1 if dom == "recover" else 0, W)
     if split > 1:
-        kname = f"zp_split_kernel<{P},{vec},{unroll},{split},{LOAD_POLICY_STREAM}>"
+        kname = f"zp_split_kernel<{P},{vec},{unroll},{split},false,{LOAD_POLICY_STREAM}>"
     else:
         kname = f"zp_{dom}_kernel<{P},{vec},{unroll},false,{LOAD_POLICY_STREAM}>"
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
