@@ -291,3 +291,47 @@ def test_rows_off_lines_many_work_groups(p, k, w, n):
         got = _recover_on_gpu(want, p, k, w, er)
         bad = [s for s in range(n) if not np.array_equal(got[s], want[s])]
         assert not bad, (v, u, t, sp, bad[:5])
+
+
+def _built(p, cfg):
+    v, u, t, sp, order = cfg
+    return (r.raid6c_unroll_mask(p, v) & u and order in (0, 1) and
+            (sp == 1 and t in (64, 128, 256) or r.raid6c_split_mask(p, v) & sp and t == 64 * sp))
+
+
+def test_autotuner_records_per_slot_and_keeps_results():
+    # The strided autotuner runs every configuration on the caller's stripes:
+    # afterwards they must still be bit-exact, and the choice is recorded for
+    # (p, op, row-size bucket) -- op + 2 for the extended Q parity -- without
+    # touching the other slots.
+    import torch
+    r.raid6c_tune_clear()
+    p, w, n = 13, 1040, 24
+    strip = (p - 1) * w
+    recorded = {}
+    try:
+        for k in (12, 20):
+            want = _stripes(p, k, w, n, seed=50 + k)
+            dev = to_dev(want.copy())
+            stride = (k + 2) * strip
+            log(f"autotune p={p} k={k} W={w} encode")
+            assert r.raid6c_autotune_n(p, k, w, dev, strip, stride, n, 0, reps=1) > 0
+            er = datagen.erasures(60 + k, n, k, "any")
+            log(f"autotune p={p} k={k} W={w} recovery")
+            assert r.raid6c_autotune_n(p, k, w, dev, strip, stride, n, 1, to_dev(er.astype(np.int32)), reps=1) > 0
+            assert np.array_equal(to_host(dev), want), k
+            base = 2 if k > p else 0
+            for op in (0, 1):
+                cfg = r.raid6c_tune_get(p, base + op, w)
+                assert _built(p, cfg), (k, op, cfg)
+                recorded[base + op] = cfg
+        # the extended run left the plain entries alone
+        assert r.raid6c_tune_get(p, 0, w) == recorded[0] and r.raid6c_tune_get(p, 1, w) == recorded[1]
+        # and the recorded configurations still give the oracle's results
+        for k in (12, 20):
+            want = _stripes(p, k, w, 8, seed=70 + k)
+            assert np.array_equal(_encode_on_gpu(want, p, k, w), want), k
+            er = datagen.erasures(80 + k, 8, k, "any")
+            assert np.array_equal(_recover_on_gpu(want, p, k, w, er), want), k
+    finally:
+        r.raid6c_tune_clear()
