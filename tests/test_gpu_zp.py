@@ -335,3 +335,53 @@ def test_autotuner_records_per_slot_and_keeps_results():
             assert np.array_equal(_recover_on_gpu(want, p, k, w, er), want), k
     finally:
         r.raid6c_tune_clear()
+
+
+def test_more_stripes_than_one_launch_holds():
+    # 2^31 threads is the most one launch takes: with 64-thread work-groups
+    # and one column tile per stripe, 2^25 stripes.  2^25 + 4096 stripes of
+    # p = 5, k = 2, 16-byte rows (8.6 GB) need a second launch; stripes on
+    # both sides of the boundary are checked against the oracle.
+    import torch
+    device()
+    p, k, w = 5, 2, 16
+    per_launch = 1 << 25
+    n = per_launch + 4096
+    strip = (p - 1) * w
+    stride = (k + 2) * strip
+    free, _ = torch.cuda.mem_get_info()
+    if free < n * stride + (8 << 30):
+        pytest.skip("needs about 17 GB of free device memory")
+    r.raid6c_tune_set(p, 0, w, 1, 1, 64)
+    r.raid6c_tune_set(p, 1, w, 1, 1, 64)
+    dev = None
+    try:
+        dev = torch.empty((n, k + 2, p - 1, w), dtype=torch.uint8, device="cuda:0")
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(91)
+        dev.random_(0, 256, generator=g)
+        sample = [0, 1, per_launch - 2, per_launch - 1, per_launch, per_launch + 1, n - 1, 12345, n - 777]
+        log(f"encode {n} stripes (two launches)")
+        r.raid6c_encode_n(p, k, w, dev, strip, stride, n)
+        torch.cuda.synchronize()
+        got = {s: to_host(dev[s]) for s in sample}
+        for s in sample:
+            want = zp.encode_stripe(got[s][None, :k], p)[0]
+            assert np.array_equal(got[s], want), s
+        # every stripe gets one of the six pairs of its 4 strips, in turn
+        pairs = np.array(list(itertools.combinations(range(k + 2), 2)), dtype=np.int32)
+        er = torch.from_numpy(pairs[np.arange(n) % len(pairs)]).to("cuda:0")
+        for s in sample:
+            for e in pairs[s % len(pairs)]:
+                dev[s, e] = to_dev(datagen.poison((p - 1, w), index=s * 8 + int(e)))
+        bad = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+        log(f"recover {n} stripes (two launches)")
+        r.raid6c_recover_n(p, k, w, dev, strip, stride, n, er, bad)
+        torch.cuda.synchronize()
+        assert int(bad.item()) == 0
+        for s in sample:
+            assert np.array_equal(to_host(dev[s]), got[s]), s
+    finally:
+        r.raid6c_tune_clear()
+        del dev
+        torch.cuda.empty_cache()
