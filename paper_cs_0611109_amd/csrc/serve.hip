@@ -356,7 +356,7 @@ void scheduler_loop(raid6c_server* s) {
     }
     // Admit requests in arrival order.  A read of a stripe whose write is in
     // flight is parked on the stripe until that write completes; a write
-    // that must wait for room, and reads of it, are skipped this round.
+    // that must wait for room, and reads of it, are skipped in this pass.
     // Later requests may pass either.
     Slot& sl = *free_slot;
     sl.reqs.clear();
