@@ -466,6 +466,11 @@ WORKLOAD_TAG = f"zp_p{P}_k{K}_w{W}_x{NSTRIPES}"
 PLAN_PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_plan -o run -- "
                     "python -u bench.py --plan-profile 10")
 PLAN_SEED, PLAN_STRIPES = 4, 20000
+# Rows on 128-byte lines against rows 16 bytes past them: strided encode at
+# p = 53, k = 26 (tuned configuration of the row-size bucket), HBM byte counters.
+ROWS_PROBE = ((2048, 503), (2064, 499), (13312, 77), (13328, 77))   # (row bytes, stripes)
+ROWS_PROBE_CMDS = {c: f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/prof_rows_{c.split('_')[0].lower()} "
+                      "-o run -- python -u bench.py --rows-probe" for c in ("FETCH_SIZE", "WRITE_SIZE")}
 
 
 def plan_jobs_bytes():
@@ -503,6 +508,66 @@ def plan_profile(runs):
     finally:
         r.raid6c_plan_destroy(plan)
     return {"plan_runs": runs, "plan_ms_mean": round(sum(ms) / len(ms), 3)}
+
+
+def rows_probe(stream):
+    """Four launches (one warm-up) of the strided encode per ROWS_PROBE row
+    size, then the 1 GiB copies that scale the byte counters."""
+    import paper_cs_0611109_amd as r
+    out = {}
+    for w, n in ROWS_PROBE:
+        b = r.StripeBatch.empty(53, 26, w, n)
+        b.tensor[:, :26].random_(0, 256)
+        ms = time_launches(lambda: b.encode(), 3, stream)
+        moved = 28 * b.strip_stride * n
+        out[w] = round(moved / (sum(ms) / len(ms) / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)
+        del b
+    copy_probe(stream)
+    return {"hbm_frac_by_row_bytes": out}
+
+
+def summarize_rows_probe(fetch_dir: str, write_dir: str, out_dir: str = None) -> dict:
+    """HBM bytes per launch of the ROWS_PROBE encodes against the bytes they
+    read and write (host-only)."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+
+    def read(d, counter):
+        zp, copies = [], []
+        for r_ in _read_csv(os.path.join(d, "run_counter_collection.csv")):
+            if r_["Counter_Name"] != counter:
+                continue
+            v = float(r_["Counter_Value"])
+            if "copyBuffer" in r_["Kernel_Name"] and v > 100000:
+                copies.append(v)
+            elif _short_name(r_["Kernel_Name"]).startswith("zp_"):
+                zp.append((int(r_["Dispatch_Id"]), v, _short_name(r_["Kernel_Name"])))
+        zp.sort()
+        if not copies or len(zp) != 4 * len(ROWS_PROBE):
+            raise RuntimeError(f"{d}: expected {4 * len(ROWS_PROBE)} encode launches and the probe copies")
+        return zp, 2**30 / (sum(copies) / len(copies) * 1024)
+
+    fetch, fs = read(fetch_dir, "FETCH_SIZE")
+    write, ws = read(write_dir, "WRITE_SIZE")
+    lines = ["# rocprofv3 HBM byte counters: strided encode, p=53 k=26, rows on 128-byte lines (2048, 13312 B)",
+             "# and 16 bytes past them (2064, 13328 B); tuned configuration of each row-size bucket",
+             "# commands (one counter per run, from the repository root, on one MI355X):",
+             "#   " + ROWS_PROBE_CMDS["FETCH_SIZE"], "#   " + ROWS_PROBE_CMDS["WRITE_SIZE"],
+             "# counters scaled by 1 GiB probe copies in the same runs: "
+             f"fetch x{fs:.4f}, write x{ws:.4f}; four launches per row size (one warm-up), averaged", "",
+             f"{'row_bytes':>10}{'stripes':>9}  {'kernel':<36}{'read_B':>13}{'fetched_B':>13}{'fetch/read':>11}"
+             f"{'written_B':>13}{'wrote_B':>13}{'ratio':>7}"]
+    table = {}
+    for i, (w, n) in enumerate(ROWS_PROBE):
+        f = sum(v for _, v, _ in fetch[4 * i:4 * i + 4]) / 4 * 1024 * fs
+        wr = sum(v for _, v, _ in write[4 * i:4 * i + 4]) / 4 * 1024 * ws
+        rd = 26 * 52 * w * n
+        wt = 2 * 52 * w * n
+        name = fetch[4 * i][2]
+        table[w] = {"kernel": name, "fetch_over_read": round(f / rd, 4), "write_over_written": round(wr / wt, 4)}
+        lines.append(f"{w:>10}{n:>9}  {name:<36}{rd:>13}{f:>13.0f}{f / rd:>11.4f}{wt:>13}{wr:>13.0f}{wr / wt:>7.4f}")
+    with open(os.path.join(out_dir, "zp_encode_kernel_rows_off_lines_p53_hbm_bytes.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return table
 
 
 def summarize_plan_profile(stats_dir: str, out_dir: str = None) -> dict:
@@ -685,12 +750,19 @@ def main():
                     help="only run the 20,000-stripe plan RUNS times (for the profiler)")
     ap.add_argument("--summarize-plan", metavar="STATS_DIR",
                     help="write the profiles/ summary of a --plan-profile run (no GPU needed)")
+    ap.add_argument("--rows-probe", action="store_true",
+                    help="only the encodes of rows on / off 128-byte lines (for the byte counters)")
+    ap.add_argument("--summarize-rows", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summary of the two --rows-probe counter runs (no GPU needed)")
     args = ap.parse_args()
     if args.summarize:
         print(json.dumps(summarize_profiles(*args.summarize), indent=1))
         return
     if args.summarize_plan:
         print(json.dumps(summarize_plan_profile(args.summarize_plan), indent=1))
+        return
+    if args.summarize_rows:
+        print(json.dumps(summarize_rows_probe(*args.summarize_rows), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (stripes are independent, "
@@ -709,6 +781,11 @@ def main():
     stream = torch.cuda.current_stream()
     if args.plan_profile:
         print(json.dumps(plan_profile(args.plan_profile)), flush=True)
+        return
+    if args.rows_probe:
+        from paper_cs_0611109_amd import autotune as at
+        at.load_cache()
+        print(json.dumps(rows_probe(stream)), flush=True)
         return
 
     log(f"allocating and filling p={P} k={K} W={W} x {NSTRIPES} stripes")
