@@ -40,8 +40,10 @@ constexpr int sk_lds_bytes_any(int V, int S) { return S * (2 * kP - 1) * 64 * V 
 static_assert(kP >= 3 && kP <= kMaxPrime && (kP % 2) == 1, "unsupported prime");
 
 // Vector widths built for this prime: wider vectors need (2p-1)*V registers
-// for the two accumulators, so they are only built for small p.
-constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (kP <= 31) ? (1 | 2) : 1;
+// for the two accumulators; vec 4 only up to p = 13.  Vec 2 for the large
+// primes runs at one wave per SIMD with one strip per batch, and on rows that
+// are a multiple of its tile it beat vec 1 by 2-6 points of peak.
+constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (1 | 2);
 
 // EXT: k > p data strips with the extended Q parity of Section 3.3.  LP: cache
 // policy of the loads (non-temporal, or the ordinary one when rows do not all
@@ -122,7 +124,9 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 // streaming pass for every case).  Jobs whose rows are not all on 128-byte lines load
 // with the ordinary cache policy (the lines at tile edges are read by two
 // waves); the others stream non-temporally.
-constexpr int kGroupVec = (kVecMask & 2) ? 2 : 1;
+// (Vec 2 only up to p = 31: above, four strips per batch at vec 2 do not fit
+// in the registers.)
+constexpr int kGroupVec = (kVecMask & 2) && kP <= 31 ? 2 : 1;
 // Strips loaded per batch: four (measured on a mix of 20,000 stripes over
 // seven primes: 2% faster than one or two, without spills up to p = 61).
 #ifdef RAID6C_GROUP_UNROLL

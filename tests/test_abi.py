@@ -170,7 +170,7 @@ def test_tuning_table():
     assert r.raid6c_tune_get(13, 0, 4096) == d0
     _err(r.raid6c_tune_set, 9, 0, 64, 1, 1, 64)
     _err(r.raid6c_tune_set, 53, 0, 64, 4, 1, 64)     # vec 4 not built for large p
-    _err(r.raid6c_tune_set, 37, 0, 64, 2, 1, 64)     # vec 2 not built above p = 31
+    _err(r.raid6c_tune_set, 53, 0, 64, 2, 2, 64)     # (2*53-1)*2 + 2*52*2 = 418 registers > 400
     _err(r.raid6c_tune_set, 13, 4, 64, 1, 1, 64)      # op 0..3
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 1, 96)
     _err(r.raid6c_tune_set, 13, 0, 64, 1, 3, 64)
