@@ -85,10 +85,19 @@ ZpConfig default_config(const ZpPrimeEntry& e, ZpKind kind, uint64_t row_bytes) 
   best.threads = lanes > 128 ? 256 : lanes > 64 ? 128 : 64;
   // Several waves per column tile (split-K) with two dwords per lane, where
   // their partials fit in LDS: fewer stripes in flight at once, which
-  // measured fastest on MI355X for the primes that allow it (p <= 29).
+  // measured fastest on MI355X for the primes that allow it (p <= 31).
   if (row_bytes >= 64 * 2 * 4) {
     if (e.split_mask[2] & 4) return ZpConfig{2, 1, 256, 4};
     if (e.split_mask[2] & 2) return ZpConfig{2, 1, 128, 2};
+  }
+  // Larger primes: two dwords per lane, one strip per batch, when the row is
+  // a whole number of such tiles (the largest work-group whose tile divides
+  // the row): p = 37..61 measured 78-80% against 72-76% for the pair chosen
+  // above.  A row with a ragged last tile keeps the pair above (a mostly
+  // empty tile costs a whole work-group).
+  if (e.has(2, 1) && row_bytes % (64 * 2 * 4) == 0) {
+    const int threads = row_bytes % (256 * 2 * 4) == 0 ? 256 : row_bytes % (128 * 2 * 4) == 0 ? 128 : 64;
+    return ZpConfig{2, 1, threads, 1};
   }
   return best;
 }
