@@ -239,3 +239,21 @@ def test_server_rejects_bad_configurations_before_device_work():
     out = ctypes.c_void_p()
     assert r.load().raid6c_server_create(ctypes.byref(cfg), ctypes.byref(out)) == r.RAID6C_E_ARG
     assert not out.value and r.raid6c_last_error()
+
+
+def test_built_in_launch_rule():
+    # With no tuned entry: split-K with vec 2 where built and the row holds a
+    # tile; above p = 31 vec 2, one strip per batch, on rows of whole
+    # 512-byte tiles (largest work-group whose tile divides the row);
+    # otherwise the most loads in flight, up to 256 threads as the row allows.
+    r.raid6c_tune_clear()
+    assert r.raid6c_tune_get(13, 1, 4096) == (2, 1, 256, 4, 0)
+    assert r.raid6c_tune_get(29, 0, 1024) == (2, 1, 128, 2, 0)
+    assert r.raid6c_tune_get(53, 0, 2048) == (2, 1, 256, 1, 0)
+    assert r.raid6c_tune_get(53, 1, 512) == (2, 1, 64, 1, 0)
+    assert r.raid6c_tune_get(37, 0, 1024) == (2, 1, 128, 1, 0)
+    assert r.raid6c_tune_get(53, 3, 13312) == (2, 1, 128, 1, 0)      # extended slots follow the same rule
+    v, u, t, sp, o = r.raid6c_tune_get(53, 0, 2064)                   # ragged last tile: not vec 2
+    assert v == 1 and sp == 1 and t == 256
+    v, u, t, sp, o = r.raid6c_tune_get(61, 0, 16)                     # 4 lanes of work: one wave
+    assert sp == 1 and t == 64
