@@ -510,6 +510,58 @@ def plan_profile(runs):
     return {"plan_runs": runs, "plan_ms_mean": round(sum(ms) / len(ms), 3)}
 
 
+P29_PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_p29 -o run -- "
+                   "python -u bench.py --p29-profile")
+P29_ROLES = ("encode", "dd", "dp", "dq")
+
+
+def p29_profile(stream, reps=10):
+    """p = 29, k = 28, 1 KiB rows, 8192 stripes: `reps` launches (after one
+    warm-up) of the encode and of the recovery of each erasure class, in
+    P29_ROLES order, for the profiler."""
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    p3, k3, w3, n3 = 29, 28, 1024, 8192
+    b = r.StripeBatch.empty(p3, k3, w3, n3)
+    b.tensor[:, :k3].random_(0, 256)
+    out = {"encode": time_launches(lambda: b.encode(), reps, stream)}
+    for kind in P29_ROLES[1:]:
+        er = torch.from_numpy(datagen.erasures(3, n3, k3, kind)).to("cuda:0")
+        out[kind] = time_launches(lambda: b.recover(er), reps, stream)
+    return {k: round(sum(v) / len(v), 4) for k, v in out.items()}
+
+
+def summarize_p29_profile(stats_dir: str, out_dir: str = None) -> dict:
+    """Per-role kernel durations of a P29_PROFILE_CMD run (host-only)."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    alg = 30 * 28 * 1024 * 8192
+    trace = [t for t in _read_csv(os.path.join(stats_dir, "run_kernel_trace.csv"))
+             if _short_name(t["Kernel_Name"]).startswith("zp_")]
+    trace.sort(key=lambda t: int(t["Start_Timestamp"]))
+    per = len(trace) // len(P29_ROLES)
+    if per * len(P29_ROLES) != len(trace) or per < 2:
+        raise RuntimeError(f"{stats_dir}: {len(trace)} Z_p launches, expected a multiple of {len(P29_ROLES)}")
+    lines = ["# rocprofv3 kernel trace: p=29, k=28, W=1024 B rows, 8192 stripes; encode, then recovery with",
+             "# per-stripe pairs of one class (dd: two data strips, dp: data + P, dq: data + Q), seed 3;",
+             "# launch configurations from paper_cs_0611109_amd/tuned_mi355x.json",
+             "# command (from the repository root, on one MI355X):", "#   " + P29_PROFILE_CMD,
+             f"# source: run_kernel_trace.csv; {per} launches per role, the first a warm-up (not averaged);",
+             f"# algorithmic bytes per launch (k+2)(p-1)W x stripes = {alg} B", "",
+             f"{'role':<8}{'kernel':<40}{'avg_ns':>11}{'GB/s':>9}{'frac':>8}"]
+    table = {}
+    for i, role in enumerate(P29_ROLES):
+        grp = trace[i * per:(i + 1) * per][1:]
+        ns = sum(int(t["End_Timestamp"]) - int(t["Start_Timestamp"]) for t in grp) / len(grp)
+        name = _short_name(grp[0]["Kernel_Name"])
+        table[role] = {"kernel": name, "avg_ns": round(ns), "frac": round(alg / ns / HBM_PEAK_GBPS, 4)}
+        lines.append(f"{role:<8}{name:<40}{ns:>11.0f}{alg / ns:>9.1f}{alg / ns / HBM_PEAK_GBPS:>8.4f}")
+    with open(os.path.join(out_dir, "zp_p29_k28_w1024_x8192_kernel_stats.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return table
+
+
 def rows_probe(stream):
     """Four launches (one warm-up) of the strided encode per ROWS_PROBE row
     size, then the 1 GiB copies that scale the byte counters."""
@@ -750,6 +802,10 @@ def main():
                     help="only run the 20,000-stripe plan RUNS times (for the profiler)")
     ap.add_argument("--summarize-plan", metavar="STATS_DIR",
                     help="write the profiles/ summary of a --plan-profile run (no GPU needed)")
+    ap.add_argument("--p29-profile", action="store_true",
+                    help="only the p = 29 encode and recoveries (for the profiler)")
+    ap.add_argument("--summarize-p29", metavar="STATS_DIR",
+                    help="write the profiles/ summary of a --p29-profile run (no GPU needed)")
     ap.add_argument("--rows-probe", action="store_true",
                     help="only the encodes of rows on / off 128-byte lines (for the byte counters)")
     ap.add_argument("--summarize-rows", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -763,6 +819,9 @@ def main():
         return
     if args.summarize_rows:
         print(json.dumps(summarize_rows_probe(*args.summarize_rows), indent=1))
+        return
+    if args.summarize_p29:
+        print(json.dumps(summarize_p29_profile(args.summarize_p29), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (stripes are independent, "
@@ -781,6 +840,11 @@ def main():
     stream = torch.cuda.current_stream()
     if args.plan_profile:
         print(json.dumps(plan_profile(args.plan_profile)), flush=True)
+        return
+    if args.p29_profile:
+        from paper_cs_0611109_amd import autotune as at
+        at.load_cache()
+        print(json.dumps(p29_profile(stream)), flush=True)
         return
     if args.rows_probe:
         from paper_cs_0611109_amd import autotune as at
