@@ -10,11 +10,14 @@ uniformly from its 91 pairs (two data strips, data + P, data + Q, or P + Q).
 `value` is user bytes made whole per second: 2 x 2.25 GiB per step.
 
 Also reported: per-kernel HIP-event timing and latency percentiles, the
-roofline of the dominant kernel (HBM bound), the GF(256) Reed-Solomon P+Q
-kernel on the same bytes, recovery throughput at p = 29, k = 28, 1 KiB rows,
-8192 stripes, 20,000 mixed stripes in one plan run against 20,000 plain
-launches, a served Poisson request stream against per-request plain launches,
-and the CPU oracle timed on a bounded sample of the workload.
+roofline of the dominant kernel (HBM bound); recovery of each erasure class
+at p = 29, k = 28, 1 KiB rows, 8192 stripes, each with its own roofline;
+launch latency at p = 5, k = 4, 64-byte rows, 1024 stripes; the GF(256)
+Reed-Solomon P+Q kernel on the same bytes, 20,000 mixed stripes in one plan
+run against 20,000 plain launches, a served Poisson request stream against
+per-request plain launches (a seeded sample of its results checked against
+the oracle); and the CPU oracle timed on a bounded sample of the workload, on
+every core and on one thread.
 """
 
 from __future__ import annotations
@@ -60,16 +63,16 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def lookup_traffic(kernel: str, cfg, bytes_per_launch: int):
-    """Measured HBM bytes per launch of `kernel` from the committed counter
-    summary, when it was taken on the current kernel source and launch
-    configuration; else None."""
+def lookup_traffic(kernel: str, cfg, bytes_per_launch: int, role: str = None):
+    """Measured HBM bytes per launch of `kernel` (in `role`, where one kernel
+    serves several) from the committed counter summaries, when they were
+    taken on the current kernel source and launch configuration; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         table = json.load(f)
-    e = table.get(kernel)
+    e = table.get(kernel if role is None else f"{kernel} {role}")
     if not e or e.get("source_sha256") != source_digest() or tuple(e.get("config", ())) != tuple(cfg):
         return None
     if e.get("algorithmic_bytes") != bytes_per_launch:
@@ -105,9 +108,11 @@ def time_launches(fn, reps, stream):
     return [a.elapsed_time(b) for a, b in evs]
 
 
-def cpu_baseline(batch, er_host, seconds: float):
-    """The CPU oracle (untuned, NumPy, one thread) on successive stripes of the
-    same workload for about `seconds`; also checks the GPU results on them."""
+def cpu_baseline(batch, er_host, seconds: float, parallel=None):
+    """The CPU oracle (untuned, NumPy) on stripes of the same workload: one
+    thread on successive stripes for about `seconds` (which also checks the
+    GPU results on them), beside the parallel run over every core
+    (`parallel`, from cpu_oracle_parallel, taken before the GPU was touched)."""
     import numpy as np
 
     import datagen
@@ -136,17 +141,74 @@ def cpu_baseline(batch, er_host, seconds: float):
                     break
     except OSError:
         pass
-    return {
-        "value": round(2 * user * done / spent / 1e9, 6),
+    one = round(2 * user * done / spent / 1e9, 6)
+    out = {
+        "value": one,
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"first {done} stripes of the workload, encode + recovery of each stripe's pair, "
                   f"NumPy oracle on one thread, {spent:.1f} s",
+        "one_thread_GBps": one,
         "host_cpus": len(os.sched_getaffinity(0)),
         "cpu_model": cpu_model,
         "gpu_results_match_oracle_on_sample": verified,
     }
+    if parallel is not None:
+        out["value"] = parallel["value"]
+        out["cores"] = parallel["workers"]
+        out["sample"] = (f"encode + recovery of each stripe's pair on the first {64 * parallel['workers']} "
+                         f"stripes of the workload, NumPy oracle in {parallel['workers']} worker processes "
+                         f"(one per core), {parallel['stripes']} stripes in {parallel['span_s']} s; "
+                         f"one thread: {one} GB/s over the first {done} stripes ({spent:.1f} s)")
+        out["parallel"] = parallel
+    return out
+
+
+def _oracle_worker(wid, nworkers, seconds, barrier, queue):
+    """One worker of the parallel CPU-oracle run: generates its share of the
+    workload's stripes (untimed), waits for the others, then runs the oracle's
+    encode + recovery over them, round after round, for about `seconds`."""
+    import datagen
+    from oracle import zp_raid as zp
+    er = datagen.erasures(SEED, NSTRIPES, K, "any")
+    mine = list(range(wid, min(NSTRIPES, 64 * nworkers), nworkers))
+    data = [(datagen.stripe_data(SEED, s, K, P, W), tuple(int(v) for v in er[s])) for s in mine]
+    barrier.wait()
+    t0 = time.time()
+    done = 0
+    while time.time() - t0 < seconds:
+        for d, e in data:
+            stripe = zp.encode_stripe(d, P)
+            bad = stripe.copy()
+            bad[list(e)] = 0
+            zp.recover(bad, P, e)
+            done += 1
+    t1 = time.time()
+    queue.put((done, t0, t1))
+
+
+def cpu_oracle_parallel(seconds: float):
+    """The CPU oracle on every core of this process's CPU set, at most 16 (the
+    host share of one GPU), one worker process each, started before anything
+    touches the GPU.  Each worker runs encode + recovery of its own stripes of
+    the workload for about `seconds`; the rate is the user bytes of all
+    workers over the span from the first start to the last end."""
+    import multiprocessing as mp
+    n = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("spawn")
+    barrier, queue = ctx.Barrier(n), ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(i, n, seconds, barrier, queue)) for i in range(n)]
+    for pr in procs:
+        pr.start()
+    got = [queue.get(timeout=600) for _ in procs]
+    for pr in procs:
+        pr.join()
+    user = K * (P - 1) * W
+    stripes = sum(g[0] for g in got)
+    span = max(g[2] for g in got) - min(g[1] for g in got)
+    return {"value": round(2 * user * stripes / span / 1e9, 6), "workers": n, "stripes": stripes,
+            "span_s": round(span, 3)}
 
 
 def extras(reps, stream):
@@ -186,28 +248,6 @@ def extras(reps, stream):
     del b
     torch.cuda.empty_cache()
 
-    # Recovery at p = 29, k = 28, 1 KiB rows, 8192 stripes.
-    p3, k3, w3, n3 = 29, 28, 1024, 8192
-    b = r.StripeBatch.empty(p3, k3, w3, n3)
-    b.tensor[:, :k3].random_(0, 256)
-    b.encode()
-    res = {}
-    for kind in ("dd", "dp", "dq"):
-        er = torch.from_numpy(datagen.erasures(3, n3, k3, kind)).to("cuda:0")
-        ms = time_launches(lambda: b.recover(er), reps, stream)
-        mean = sum(ms) / len(ms)
-        res[kind] = {
-            "GBps_user": round(b.user_bytes / (mean / 1e3) / 1e9, 1),
-            "hbm_frac": round((k3 + 2) * b.strip_stride * n3 / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-            "ms_p50": round(pct(ms, 50), 4), "ms_p99": round(pct(ms, 99), 4),
-        }
-    ms = time_launches(lambda: b.encode(), reps, stream)
-    mean = sum(ms) / len(ms)
-    res["encode"] = {"GBps_user": round(b.user_bytes / (mean / 1e3) / 1e9, 1),
-                     "hbm_frac": round((k3 + 2) * b.strip_stride * n3 / (mean / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}
-    out["p29_k28_w1024_x8192"] = res
-    del b
-    torch.cuda.empty_cache()
     # The remaining figures are independent: one that fails is recorded as
     # such and the others are still measured.
     for name, fn in (("extended_q_parity", lambda: extended(reps, stream)),
@@ -222,6 +262,107 @@ def extras(reps, stream):
             out[name] = {"error": str(e)}
         torch.cuda.empty_cache()
     return out
+
+
+P3, K3, W3, N3, SEED3 = 29, 28, 1024, 8192, 3
+CONFIG3_ROLES = ("dd", "dp", "dq", "encode")
+
+
+def config3(reps, stream):
+    """Recovery at p = 29, k = 28, 1 KiB rows, 8192 stripes (6.125 GiB of user
+    data): per-stripe pairs of one class per launch (dd: two data strips
+    uniform over the 378 pairs; dp / dq: a data strip uniform over the 28,
+    plus P / Q), and the encode of the same stripes.  Per role: user GB/s,
+    fraction of HBM peak over the algorithmic bytes, and a roofline object
+    (HIP-event mean launch duration; HBM bytes from the committed counter
+    summary when it was taken on the current kernel sources)."""
+    import torch
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    b = r.StripeBatch.empty(P3, K3, W3, N3)
+    b.tensor[:, :K3].random_(0, 256)
+    b.encode()
+    alg = (K3 + 2) * b.strip_stride * N3
+    res = {"workload": f"Z_p-RAID recovery, p={P3} k={K3} W={W3} B x {N3} stripes, one erasure class per launch",
+           "user_bytes_per_launch": b.user_bytes, "algorithmic_bytes_per_launch": alg}
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    for role in CONFIG3_ROLES:
+        if role == "encode":
+            ms = time_launches(lambda: b.encode(), reps, stream)
+            op = 0
+        else:
+            er = torch.from_numpy(datagen.erasures(SEED3, N3, K3, role)).to("cuda:0")
+            ms = time_launches(lambda: b.recover(er, bad), reps, stream)
+            op = 1
+        mean = sum(ms) / len(ms)
+        vec, unroll, threads, split, order = r.raid6c_tune_get(P3, op, W3)
+        kname = _kernel_name(P3, op, vec, unroll, split)
+        achieved = alg / (mean / 1e3) / 1e9
+        res[role] = {
+            "GBps_user": round(b.user_bytes / (mean / 1e3) / 1e9, 1),
+            "hbm_frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "ms_p50": round(pct(ms, 50), 4), "ms_p99": round(pct(ms, 99), 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                         "traffic": lookup_traffic(kname, (vec, unroll, threads, split, order), alg, role),
+                         "kernel": kname, "avg_launch_ms": round(mean, 4),
+                         "launch": {"vec": vec, "unroll": unroll, "threads": threads, "split": split,
+                                    "order": order}},
+        }
+    torch.cuda.synchronize()
+    if int(bad.item()) != 0:
+        raise RuntimeError("p = 29 recovery rejected erasure entries")
+    del b
+    torch.cuda.empty_cache()
+    return res
+
+
+def _kernel_name(p, op, vec, unroll, split, ext=False):
+    """Name (as the profiler shows it) of the strided Z_p kernel a launch
+    configuration selects, for rows on 128-byte lines."""
+    e = "true" if ext else "false"
+    if split > 1:
+        return f"zp_split_kernel<{p},{vec},{unroll},{split},{e},{LOAD_POLICY_STREAM}>"
+    kind = "encode" if op in (0, 2) else "recover"
+    return f"zp_{kind}_kernel<{p},{vec},{unroll},{e},{LOAD_POLICY_STREAM}>"
+
+
+def config1_latency(reps, stream):
+    """p = 5, k = 4, W = 64 B, 1024 stripes (1 MiB of user data: cache-resident,
+    launch-bound): per-launch latency of the encode and of the recovery of each
+    of the 15 strip pairs among the 6 strips (the same pair on every stripe).
+    kernel_ms: HIP events around the launch on its stream; call_ms: host time
+    from the call to the end of a stream synchronize."""
+    import torch
+
+    import paper_cs_0611109_amd as r
+    b = r.StripeBatch.empty(5, 4, 64, 1024)
+    b.tensor[:, :4].random_(0, 256)
+    b.encode()
+    ops = [("encode", None)] + [(f"{a},{c}", (a, c)) for a in range(6) for c in range(a + 1, 6)]
+    per, allk, allc = {}, [], []
+    for name, pair in ops:
+        if pair is None:
+            fn = b.encode
+        else:
+            er = torch.tensor([pair] * 1024, dtype=torch.int32, device="cuda:0")
+            fn = (lambda er=er: b.recover(er))
+        kms = time_launches(fn, reps, stream)
+        cms = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            stream.synchronize()
+            cms.append((time.perf_counter() - t0) * 1e3)
+        allk += kms
+        allc += cms
+        per[name] = {"kernel_ms_p50": round(pct(kms, 50), 4), "kernel_ms_p99": round(pct(kms, 99), 4),
+                     "call_ms_p50": round(pct(cms, 50), 4), "call_ms_p99": round(pct(cms, 99), 4)}
+    del b
+    return {"workload": "p=5 k=4 W=64 B x 1024 stripes; encode + each of the 15 pairs", "launches_per_op": reps,
+            "kernel_ms_p50": round(pct(allk, 50), 4), "kernel_ms_p99": round(pct(allk, 99), 4),
+            "call_ms_p50": round(pct(allc, 50), 4), "call_ms_p99": round(pct(allc, 99), 4), "by_op": per}
 
 
 def extended(reps, stream):
@@ -348,12 +489,41 @@ def served_poisson(n=4000, seed=5):
     arr = (r.raid6c_request * n)(*creq)
     base_t = [q.arrival_s for q in reqs]
     torch.cuda.synchronize()
+    # A seeded sample of requests whose results are copied to the host after
+    # every run, for the oracle check of the CPU-baseline leg; the payloads
+    # they depend on too.
+    d = datagen.Draws(seed, datagen.TAG_POISON, 7)
+    sample = sorted({d.below(n) for _ in range(SERVE_SAMPLE)})
+    need = {i if reqs[i].kind == "write" else reqs[i].target for i in sample}
+    payloads = {}
+    for i in need:
+        q = reqs[i]
+        nb = q.k * (q.p - 1) * q.row_bytes
+        payloads[i] = pay[pay_off[i]:pay_off[i] + nb].cpu().numpy().reshape(q.k, q.p - 1, q.row_bytes)
+    _SERVED_SAMPLES.clear()
 
-    def run(plain, times):
+    def grab(name, srv, comps):
+        got = []
+        for i in sample:
+            q = reqs[i]
+            if comps[i].status != r.RAID6C_ST_OK:
+                got.append((i, None))
+                continue
+            strip = (q.p - 1) * q.row_bytes
+            if q.kind == "write":
+                base, stride = r.raid6c_server_stripe(srv, i)
+                got.append((i, _device_bytes(base, (q.k + 2) * stride)))
+            else:
+                ne = 2 if q.e1 >= 0 else 1
+                got.append((i, outb[out_off[i]:out_off[i] + ne * strip].cpu().numpy()))
+        _SERVED_SAMPLES.append((name, got))
+
+    def run(plain, times, name):
         srv = r.raid6c_server_create(8 << 30, max_inflight=32 if plain else 8, max_batch=64, plain=plain)
         try:
             comps = r.raid6c_server_replay(srv, arr, times)
             st = r.raid6c_server_get_stats(srv)
+            grab(name, srv, comps)
         finally:
             r.raid6c_server_destroy(srv)
         bad = sum(c.status != r.RAID6C_ST_OK for c in comps)
@@ -364,16 +534,75 @@ def served_poisson(n=4000, seed=5):
                 "batches": st.batches, "failed": bad}
 
     zero = [0.0] * n
-    sat_plain = run(True, zero)
-    sat_served = run(False, zero)
+    sat_plain = run(True, zero, "saturation_plain")
+    sat_served = run(False, zero, "saturation_served")
     rate = 0.8 * sat_plain["requests_per_s"]
     times = [t / rate for t in base_t]
     high = 4.0 * sat_plain["requests_per_s"]
+    _SERVED_SAMPLES.append(("payloads", (reqs, payloads)))
     return {"requests": n, "writes": sum(q.kind == "write" for q in reqs),
             "saturation_plain": sat_plain, "saturation_served": sat_served,
-            "qps": round(rate, 1), "served_at_qps": run(False, times), "plain_at_qps": run(True, times),
+            "qps": round(rate, 1), "served_at_qps": run(False, times, "served_at_qps"),
+            "plain_at_qps": run(True, times, "plain_at_qps"),
             "qps_4x_plain_saturation": round(high, 1),
-            "served_at_4x": run(False, [t / high for t in base_t])}
+            "served_at_4x": run(False, [t / high for t in base_t], "served_at_4x"),
+            "verified_against_oracle": None}
+
+
+# (run name, [(request index, host bytes or None)]) of the last served_poisson
+# call, and ("payloads", (requests, {write index: data strips})).
+_SERVED_SAMPLES = []
+SERVE_SAMPLE = 32
+
+
+def _device_bytes(addr, n):
+    """n bytes at a raw device address (inside the server's store), on the host."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    out = np.empty(n, dtype=np.uint8)
+    torch.cuda.synchronize()
+    if hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(addr), n, 2) != 0:   # device to host
+        raise RuntimeError("hipMemcpy from the stripe store failed")
+    return out
+
+
+def verify_served_samples():
+    """Oracle check of the served_poisson sample (part of the CPU-baseline
+    leg): every sampled write's stored stripe equals the oracle's encode of
+    its payload, and every sampled degraded read's rebuilt strips equal the
+    oracle's strips of the stripe it read."""
+    import numpy as np
+
+    from oracle import zp_raid as zp
+    runs = [x for x in _SERVED_SAMPLES if x[0] != "payloads"]
+    pl = [x[1] for x in _SERVED_SAMPLES if x[0] == "payloads"]
+    if not runs or not pl:
+        return None
+    reqs, payloads = pl[0]
+    want = {i: zp.encode_stripe(d, reqs[i].p) for i, d in payloads.items()}
+    checked, bad, skipped = 0, [], 0
+    for name, got in runs:
+        for i, buf in got:
+            q = reqs[i]
+            if buf is None:
+                skipped += 1
+                continue
+            if q.kind == "write":
+                ok = np.array_equal(buf.reshape(want[i].shape), want[i])
+            else:
+                w = want[q.target]
+                es = sorted(e for e in (q.e0, q.e1) if e >= 0)
+                ok = np.array_equal(buf.reshape(len(es), q.p - 1, q.row_bytes), w[es])
+            checked += 1
+            if not ok:
+                bad.append((name, i))
+    return {"checked": checked, "not_completed_ok": skipped, "mismatches": len(bad), "match": not bad and skipped == 0,
+            "sample": f"{SERVE_SAMPLE} seeded request draws per run, {len(runs)} runs; writes: the stored stripe "
+                      "(data + P + Q), reads: the rebuilt strips"}
 
 
 def batched_mixed(reps, stream):
@@ -515,10 +744,14 @@ P29_PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpur
 P29_ROLES = ("encode", "dd", "dp", "dq")
 
 
+P29_PMC_CMDS = {c: f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/prof_p29_{c.split('_')[0].lower()} "
+                   "-o run -- python -u bench.py --p29-profile --copy-probe" for c in ("FETCH_SIZE", "WRITE_SIZE")}
+
+
 def p29_profile(stream, reps=10):
     """p = 29, k = 28, 1 KiB rows, 8192 stripes: `reps` launches (after one
     warm-up) of the encode and of the recovery of each erasure class, in
-    P29_ROLES order, for the profiler."""
+    P29_ROLES order, for the profiler (the erasure draws of config3)."""
     import torch
 
     import datagen
@@ -560,6 +793,75 @@ def summarize_p29_profile(stats_dir: str, out_dir: str = None) -> dict:
     with open(os.path.join(out_dir, "zp_p29_k28_w1024_x8192_kernel_stats.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     return table
+
+
+def summarize_p29_counters(fetch_dir: str, write_dir: str, out_dir: str = None) -> dict:
+    """HBM bytes per launch of the P29_PMC_CMDS runs against the algorithmic
+    bytes, per role, and their entries in the traffic table (host-only)."""
+    import re
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    alg = (K3 + 2) * (P3 - 1) * W3 * N3
+
+    def read(d, counter):
+        zp, copies, wg = [], [], {}
+        for r_ in _read_csv(os.path.join(d, "run_counter_collection.csv")):
+            if r_["Counter_Name"] != counter:
+                continue
+            v = float(r_["Counter_Value"])
+            if "copyBuffer" in r_["Kernel_Name"]:
+                if v > 100000:
+                    copies.append(v)
+                continue
+            n = _short_name(r_["Kernel_Name"])
+            if n.startswith("zp_"):
+                zp.append((int(r_["Dispatch_Id"]), v, n))
+                wg[n] = int(r_["Workgroup_Size"])
+        zp.sort()
+        if not copies or len(zp) % len(P29_ROLES) != 0:
+            raise RuntimeError(f"{d}: {len(zp)} Z_p launches, expected a multiple of {len(P29_ROLES)}, and probe copies")
+        return zp, 2**30 / (sum(copies) / len(copies) * 1024), wg
+
+    fetch, fs, wg = read(fetch_dir, "FETCH_SIZE")
+    write, ws, _ = read(write_dir, "WRITE_SIZE")
+    per = len(fetch) // len(P29_ROLES)
+    lines = ["# rocprofv3 HBM byte counters: p=29, k=28, W=1024 B rows, 8192 stripes; encode, then recovery",
+             "# with per-stripe pairs of one class (dd, dp, dq; seed 3); launch configurations from",
+             "# paper_cs_0611109_amd/tuned_mi355x.json",
+             "# commands (one counter per run, from the repository root, on one MI355X):",
+             "#   " + P29_PMC_CMDS["FETCH_SIZE"], "#   " + P29_PMC_CMDS["WRITE_SIZE"],
+             f"# counters scaled by 1 GiB probe copies in the same runs: fetch x{fs:.4f}, write x{ws:.4f};",
+             f"# {per} launches per role (the first a warm-up, not averaged); algorithmic bytes per launch",
+             f"# (k+2)(p-1)W x stripes = {alg} B", "",
+             f"{'role':<8}{'kernel':<40}{'fetch_KiB':>11}{'write_KiB':>11}{'hbm_B':>13}{'ratio':>9}"]
+    path = os.path.join(out_dir, "traffic.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    digest = source_digest()
+    import paper_cs_0611109_amd as r
+    from paper_cs_0611109_amd import autotune as at
+    at.load_cache()
+    res = {}
+    for i, role in enumerate(P29_ROLES):
+        f = [v for _, v, _ in fetch[i * per:(i + 1) * per][1:]]
+        w = [v for _, v, _ in write[i * per:(i + 1) * per][1:]]
+        name = fetch[i * per][2]
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
+        hbm = int(round(fk * 1024 * fs + wk * 1024 * ws))
+        lines.append(f"{role:<8}{name:<40}{fk:>11.0f}{wk:>11.0f}{hbm:>13}{hbm / alg:>9.5f}")
+        m = re.match(r"zp_(\w+)_kernel<(\d+), (\d+), (\d+), (\w+)(?:, \w+)*>", name)
+        split = int(m.group(5)) if m.group(1) == "split" else 1
+        op = 0 if role == "encode" else 1
+        cfg = list(r.raid6c_tune_get(P3, op, W3))
+        key = f"{name.replace(', ', ',')} {role}"
+        table[key] = {"source_sha256": digest, "config": cfg, "algorithmic_bytes": alg, "hbm_bytes_per_launch": hbm,
+                      "fetch_kib": round(fk), "write_kib": round(wk), "fetch_scale": round(fs, 4),
+                      "write_scale": round(ws, 4), "summary": "profiles/zp_p29_k28_w1024_x8192_hbm_bytes.txt",
+                      "workgroup": wg.get(name), "split": split}
+        res[role] = {"kernel": name, "ratio": round(hbm / alg, 5)}
+    with open(os.path.join(out_dir, "zp_p29_k28_w1024_x8192_hbm_bytes.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1)
+    return res
 
 
 def rows_probe(stream):
@@ -806,6 +1108,8 @@ def main():
                     help="only the p = 29 encode and recoveries (for the profiler)")
     ap.add_argument("--summarize-p29", metavar="STATS_DIR",
                     help="write the profiles/ summary of a --p29-profile run (no GPU needed)")
+    ap.add_argument("--summarize-p29-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ HBM-byte summary of the two --p29-profile counter runs (no GPU needed)")
     ap.add_argument("--rows-probe", action="store_true",
                     help="only the encodes of rows on / off 128-byte lines (for the byte counters)")
     ap.add_argument("--summarize-rows", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -820,6 +1124,9 @@ def main():
     if args.summarize_rows:
         print(json.dumps(summarize_rows_probe(*args.summarize_rows), indent=1))
         return
+    if args.summarize_p29_counters:
+        print(json.dumps(summarize_p29_counters(*args.summarize_p29_counters), indent=1))
+        return
     if args.summarize_p29:
         print(json.dumps(summarize_p29_profile(args.summarize_p29), indent=1))
         return
@@ -828,6 +1135,12 @@ def main():
               "so more GPUs would shard stripes with no communication; see the design notes).",
               file=sys.stderr)
         sys.exit(2)
+    # The CPU oracle over every core runs first, in worker processes started
+    # before torch is imported and before anything touches the GPU.
+    parallel = None
+    if not (args.no_cpu_baseline or args.plan_profile or args.p29_profile or args.rows_probe):
+        log("cpu baseline: oracle on every core (worker processes, before the GPU is touched)")
+        parallel = cpu_oracle_parallel(max(1.0, args.cpu_seconds / 8))
 
     import torch
 
@@ -844,7 +1157,10 @@ def main():
     if args.p29_profile:
         from paper_cs_0611109_amd import autotune as at
         at.load_cache()
-        print(json.dumps(p29_profile(stream)), flush=True)
+        res = p29_profile(stream)
+        if args.copy_probe:
+            copy_probe(stream)
+        print(json.dumps(res), flush=True)
         return
     if args.rows_probe:
         from paper_cs_0611109_amd import autotune as at
@@ -937,12 +1253,21 @@ def main():
         "roofline": roofline,
         "autotune": tuned,
     }
+    log(f"recovery at p={P3} k={K3} W={W3} x {N3} stripes, by erasure class")
+    result["recover_config3"] = config3(max(20, args.steps), stream)
+    log("launch latency at p=5 k=4 W=64 x 1024 stripes")
+    result["latency_config1"] = config1_latency(50, stream)
     if not args.no_extras:
-        log("extras: GF(256) RS comparison and p=29 recovery")
+        log("extras: GF(256) RS comparison, extended parity, small writes, Z17 layout, plans, server")
         result["extras"] = extras(max(10, args.steps // 2), stream)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for about {args.cpu_seconds:.0f} s")
-        result["cpu_baseline"] = cpu_baseline(batch, er_host, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(batch, er_host, args.cpu_seconds, parallel)
+        served = result.get("extras", {}).get("served_poisson")
+        if isinstance(served, dict) and "error" not in served:
+            log("cpu baseline: oracle check of the served sample")
+            served["verified_against_oracle"] = verify_served_samples()
+            result["cpu_baseline"]["served_sample_matches_oracle"] = (served["verified_against_oracle"] or {}).get("match")
     else:
         result["cpu_baseline"] = None
     if args.copy_probe:

@@ -440,6 +440,7 @@ typedef struct raid6c_server_stats {
   uint64_t user_bytes;   /* k*(p-1)*row_bytes of every successful request */
   uint64_t resident;     /* stripes in the store */
   uint64_t store_used;   /* bytes they occupy */
+  uint64_t table_grows;  /* batches whose slot had to enlarge its job/item tables */
 } raid6c_server_stats;
 
 typedef struct raid6c_server raid6c_server;

@@ -199,12 +199,14 @@ size_t table_bytes(size_t jobs, size_t items) {
 
 // Make room for a batch's tables; a new device block starts with a zeroed
 // counter.  Called without the lock, on the slot's stream being idle.  The
+// first call sizes the tables exactly; later ones at least double them.  The
 // outgrown buffers are kept until the server is destroyed: freeing them now
 // would synchronise the whole device and stall every batch in flight.
-bool grow_slot(Slot& sl, size_t jobs, size_t items) {
+bool grow_slot(Slot& sl, size_t jobs, size_t items, bool* grew = nullptr) {
   const size_t need = table_bytes(jobs, items);
   if (need <= sl.cap) return true;
-  const size_t cap = std::max(need, sl.cap * 2 + 65536);
+  if (grew != nullptr) *grew = sl.cap != 0;
+  const size_t cap = sl.cap == 0 ? need : std::max(need, sl.cap * 2);
   if (sl.h_buf) sl.retired_h.push_back(sl.h_buf);
   if (sl.d_mem) sl.retired_d.push_back(sl.d_mem);
   sl.h_buf = nullptr;
@@ -425,10 +427,12 @@ void scheduler_loop(raid6c_server* s) {
     s->stats.batches++;
     lk.unlock();
     hipError_t e = hipSuccess;
-    if (!s->cfg.plain && !grow_slot(sl, sl.reqs.size(), items)) e = hipErrorOutOfMemory;
+    bool grew = false;
+    if (!s->cfg.plain && !grow_slot(sl, sl.reqs.size(), items, &grew)) e = hipErrorOutOfMemory;
     sl.launch_ns = s->now_ns();
     if (e == hipSuccess) e = launch_slot(s, sl);
     lk.lock();
+    if (grew) s->stats.table_grows++;
     if (e == hipSuccess) {
       sl.launched = true;
       s->cv_done.notify_all();

@@ -147,6 +147,73 @@ def test_alone_and_in_the_mix_are_identical():
         assert np.array_equal(s0[k], s1[k]) and np.array_equal(s0[k], s2[k]) and np.array_equal(s0[k], s3[k])
 
 
+# The served workload's own payload range (4 KiB - 4 MiB, log-uniform): rows
+# reach 41 KB at p = 11.  Slot tables start at max_batch x 64 column tiles of
+# 256 bytes, so with two requests per batch any request with rows over 32 KiB
+# (and many pairs over 16 KiB) makes its slot enlarge its tables, while the
+# other slots' batches are in flight.
+FULL_SEED, FULL_N = 41, 300
+
+
+def _full_trace():
+    reqs = datagen.serve_requests(FULL_SEED, FULL_N, qps=200000.0)   # default pay_hi = 4 MiB
+    assert max(q.payload for q in reqs) > 3 << 20
+    assert sum(q.kind == "write" and q.row_bytes > 32768 for q in reqs) >= 1
+    return reqs
+
+
+@pytest.mark.parametrize("mode", ["grouped", "persistent"])
+def test_full_size_payloads_grow_tables_and_match_oracle(mode):
+    device()
+    reqs = _full_trace()
+    c, pay, out, out_off, data = _stage(reqs, FULL_SEED)
+    stripes = _expected_stripes(reqs, data)
+    srv = r.raid6c_server_create(4 << 30, max_inflight=4, max_batch=2, persistent=mode == "persistent")
+    try:
+        comps = r.raid6c_server_replay(srv, c, [q.arrival_s for q in reqs])
+        st = r.raid6c_server_get_stats(srv)
+        log(f"{mode}: {st.batches} batches, {st.table_grows} table enlargements, "
+            f"largest row {max(q.row_bytes for q in reqs)} B")
+        assert st.table_grows >= 1
+        _check(srv, reqs, comps, out, out_off, stripes)
+    finally:
+        r.raid6c_server_destroy(srv)
+
+
+def test_full_size_payloads_alone_and_in_the_mix_are_identical():
+    """Each request alone (one plain launch) and in batches of up to 16, in
+    both launch modes: the same rebuilt strips and stored stripes, all equal
+    to the oracle's."""
+    import torch
+    device()
+    reqs = _full_trace()
+    results = []
+    for plain, inflight, batch, persistent in ((True, 8, 1, False), (False, 4, 16, False), (False, 4, 16, True)):
+        c, pay, out, out_off, data = _stage(reqs, FULL_SEED)
+        stripes = _expected_stripes(reqs, data)
+        srv = r.raid6c_server_create(4 << 30, max_inflight=inflight, max_batch=batch, plain=plain,
+                                     persistent=persistent)
+        try:
+            comps = r.raid6c_server_replay(srv, c, [q.arrival_s for q in reqs])
+            _check(srv, reqs, comps, out, out_off, stripes)
+            stored = {}
+            for q in reqs:
+                if q.kind == "write":
+                    base, stride = r.raid6c_server_stripe(srv, q.index)
+                    n = (q.k + 2) * stride
+                    stored[q.index] = _read_device(base, n, torch.empty(n, dtype=torch.uint8, device="cuda:0"))
+            results.append((to_host(out), stored, max(x.batch_size for x in comps)))
+        finally:
+            r.raid6c_server_destroy(srv)
+        del pay, out
+    (o0, s0, b0), (o1, s1, b1), (o2, s2, b2) = results
+    log(f"largest batches: plain {b0}, grouped {b1}, persistent {b2}")
+    assert b0 == 1 and b1 > 1 and b2 > 1
+    assert np.array_equal(o0, o1) and np.array_equal(o0, o2)
+    for k in s0:
+        assert np.array_equal(s0[k], s1[k]) and np.array_equal(s0[k], s2[k])
+
+
 def test_small_budget_evicts_oldest_and_reports_not_resident():
     device()
     reqs = _trace(33, 200, qps=5000.0)
