@@ -367,6 +367,30 @@ int raid6c_plan_destroy(raid6c_plan* plan);
  * launched.  Errors: as raid6c_plan_create. */
 int raid6c_run_jobs(const raid6c_job* jobs, size_t njobs, void* stream);
 
+/* Limits of raid6c_run_jobs_noalloc: jobs per call, and column tiles per call
+ * (a job has ceil(row_bytes / 512) tiles for p <= 31, ceil(row_bytes / 256)
+ * above). */
+#define RAID6C_NOALLOC_MAX_JOBS 4096
+#define RAID6C_NOALLOC_MAX_ITEMS 262144
+
+/* For callers that cannot allocate (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the jobs of a job list run as a
+ * plan's grouped schedule runs them (one grid of each prime's job-list
+ * kernel, on `stream`), with the same results, but nothing is allocated.  The
+ * job and item tables are staged in a fixed device array of about 2.3 MiB
+ * that the library holds on each GPU it runs on until the process ends, and
+ * in a fixed host array.  Jobs are checked as by raid6c_run_jobs (not for
+ * overlap: strips of different jobs must not share bytes); on an invalid job,
+ * or beyond RAID6C_NOALLOC_MAX_JOBS jobs or RAID6C_NOALLOC_MAX_ITEMS tiles
+ * (RAID6C_E_ARG), nothing is launched.  The tables are copied from pageable
+ * host memory, which the runtime does synchronously: the call returns after
+ * the copy, which waits for the work queued before it on `stream`.  Calls on
+ * one stream are therefore ordered; calls on one GPU whose work overlaps
+ * (different streams, or host threads that do not wait for each other's
+ * work) share the one device array and race.  Errors: as raid6c_run_jobs,
+ * RAID6C_E_HIP. */
+int raid6c_run_jobs_noalloc(const raid6c_job* jobs, size_t njobs, void* stream);
+
 /* ------------------------------------------------------------------------
  * Request server: continuous batching of writes and degraded reads
  *

@@ -63,6 +63,7 @@ SIGNATURES = {
     "raid6c_plan_autotune": (_c_int, [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_float)]),
     "raid6c_plan_destroy": (_c_int, [_vp]),
     "raid6c_run_jobs": (_c_int, [_vp, _c_size, _vp]),
+    "raid6c_run_jobs_noalloc": (_c_int, [_vp, _c_size, _vp]),
     "raid6c_server_create": (_c_int, [_vp, _vp]),
     "raid6c_server_submit": (_c_int, [_vp, _vp, _c_size]),
     "raid6c_server_poll": (_c_int, [_vp, _vp, _c_size, ctypes.POINTER(_c_size)]),
@@ -368,6 +369,18 @@ def raid6c_run_jobs(jobs, stream=None):
     """Every job as its own plain launch (the per-request path)."""
     arr = jobs if isinstance(jobs, ctypes.Array) else (raid6c_job * len(jobs))(*jobs)
     return _check(load().raid6c_run_jobs(ctypes.cast(arr, _vp) if len(arr) else None, len(arr), _stream(stream)))
+
+
+def raid6c_run_jobs_noalloc(jobs, stream=None):
+    """The jobs as a plan's grouped schedule runs them, tables staged in the
+    library's fixed device array (nothing allocated)."""
+    arr = jobs if isinstance(jobs, ctypes.Array) else (raid6c_job * len(jobs))(*jobs)
+    return _check(load().raid6c_run_jobs_noalloc(ctypes.cast(arr, _vp) if len(arr) else None, len(arr),
+                                                 _stream(stream)))
+
+
+RAID6C_NOALLOC_MAX_JOBS = 4096
+RAID6C_NOALLOC_MAX_ITEMS = 262144
 
 
 def raid6c_autotune_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, op, erasures=None, reps=5,

@@ -29,7 +29,8 @@ CFLAGS = [
 ]
 
 # Plain (non-templated-per-prime) sources.
-SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip", "update.hip", "layout.hip", "batch.hip", "serve.hip"]
+SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip", "update.hip", "layout.hip", "batch.hip", "serve.hip",
+           "noalloc.hip"]
 
 
 def _units(build_dir):

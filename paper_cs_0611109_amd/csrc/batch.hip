@@ -264,7 +264,9 @@ int build_graph(raid6c_plan* pl) {
   return RAID6C_OK;
 }
 
-int check_job(const raid6c_job& J, size_t i, Case* out) {
+}  // namespace
+
+int raid6c::check_job(const raid6c_job& J, size_t i, Case* out) {
   const int p = J.p, k = J.k;
   if (!is_odd_prime(p)) return fail(RAID6C_E_ARG, "job %zu: p = %d is not an odd prime", i, p);
   if (p > kMaxPrime) return fail(RAID6C_E_UNSUPPORTED, "job %zu: p = %d is not built", i, p);
@@ -288,6 +290,24 @@ int check_job(const raid6c_job& J, size_t i, Case* out) {
   *out = cs;
   return RAID6C_OK;
 }
+
+BatchJob raid6c::make_batch_job(const raid6c_job& J, const Case& cs) {
+  BatchJob b{};
+  b.base = (uint8_t*)J.base;
+  b.strip_stride = J.strip_stride;
+  b.row_bytes = J.row_bytes;
+  b.p = (int16_t)J.p;
+  b.k = (int16_t)J.k;
+  b.op = (int16_t)cs.op;
+  b.x = (int16_t)cs.x;
+  b.y = (int16_t)cs.y;
+  b.e0 = -1;
+  b.e1 = -1;
+  b.src = nullptr;
+  return b;
+}
+
+namespace {
 
 bool valid_schedule(const raid6c_schedule& s) {
   return s.waves_per_cu >= 1 && s.waves_per_cu <= 32 && s.chunk >= 1 && s.chunk <= 1024 &&
@@ -324,19 +344,7 @@ int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) 
       delete pl;
       return rc;
     }
-    BatchJob b{};
-    b.base = (uint8_t*)J.base;
-    b.strip_stride = J.strip_stride;
-    b.row_bytes = J.row_bytes;
-    b.p = (int16_t)p;
-    b.k = (int16_t)k;
-    b.op = (int16_t)cs.op;
-    b.x = (int16_t)cs.x;
-    b.y = (int16_t)cs.y;
-    b.e0 = -1;
-    b.e1 = -1;
-    b.src = nullptr;
-    pl->jobs.push_back(b);
+    pl->jobs.push_back(make_batch_job(J, cs));
     const uint64_t strip = (uint64_t)(p - 1) * J.row_bytes;
     const int moved = (cs.op == OP_P || cs.op == OP_Q || cs.op == OP_D) ? k + 1 : k + 2;
     pl->bytes += (uint64_t)moved * strip;

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+struct raid6c_job;  // include/raid6c.h
+
 namespace raid6c {
 
 // Largest prime built into the GPU path (odd primes 3..61).
@@ -171,6 +173,13 @@ constexpr int kBatchTileBytes = 256;  // 64 lanes x one dword
 // Enqueue the persistent kernel on `stream` (grid work-groups of one wave,
 // LDS for primes up to max_p); the counter must hold a.base.
 hipError_t batch_launch(const BatchArgs& a, int grid, int max_p, hipStream_t stream);
+
+// Checks of one job of a job list (batch.hip): *out receives its case.
+// Returns RAID6C_OK or an error code (the message names job i).
+int check_job(const ::raid6c_job& J, size_t i, Case* out);
+// The device-side description of a checked job (in place: no redirected
+// strips, no payload source).
+BatchJob make_batch_job(const ::raid6c_job& J, const Case& cs);
 
 // Kernel functions, for graph nodes.
 const void* batch_kernel_fn();

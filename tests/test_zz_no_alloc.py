@@ -1,0 +1,96 @@
+"""GPU test of raid6c_run_jobs_noalloc, the entry point that allocates nothing:
+its results equal those of the plan it stands in for (raid6c_plan_create +
+raid6c_plan_run, grouped schedule), bit for bit, on two calls in a row, the
+second smaller than the first (the fixed device array keeps the first call's
+tables); and calls beyond its limits are refused before any work."""
+
+import pytest
+
+import datagen
+import paper_cs_0611109_amd as r
+from gpu_util import device, log
+
+pytestmark = pytest.mark.gpu
+
+PRIMES = [3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61]
+
+
+def _specs(seed, n, w_max):
+    """Mixed geometries over every prime, every job kind, ragged rows (some
+    off 128-byte lines)."""
+    d = datagen.Draws(seed, datagen.TAG_GEOMETRY, 2)
+    out = []
+    for _ in range(n):
+        p = PRIMES[d.below(len(PRIMES))]
+        k = d.between(1, p)
+        w = 16 * d.between(1, w_max // 16)
+        kind = d.below(3)
+        if kind == 0:
+            out.append((r.RAID6C_JOB_ENCODE, p, k, -1, -1, w))
+        elif kind == 1:
+            out.append((r.RAID6C_JOB_RECOVER, p, k, d.below(k + 2), -1, w))
+        else:
+            a = d.below(k + 2)
+            b = d.below(k + 1)
+            b += b >= a
+            out.append((r.RAID6C_JOB_RECOVER, p, k, a, b, w))
+    return out
+
+
+def _jobs(specs, base):
+    """Jobs on one buffer: stripes back to back with a 48-byte gap after each
+    strip; also returns the buffer size."""
+    up = lambda x: (x + 15) // 16 * 16
+    jobs, pos = [], 0
+    for op, p, k, e0, e1, w in specs:
+        stride = up((p - 1) * w + 48)
+        jobs.append(r.raid6c_job(op, p, k, e0, e1, w, stride, base + pos))
+        pos = up(pos + (k + 2) * stride + 64)
+    return jobs, pos
+
+
+def _compare_once(specs, seed):
+    import torch
+    _, total = _jobs(specs, 0)
+    src = torch.empty(total, dtype=torch.uint8, device="cuda:0")
+    src.random_(0, 256, generator=torch.Generator(device="cuda:0").manual_seed(seed))
+    a, b = src.clone(), src.clone()
+    ja, _ = _jobs(specs, a.data_ptr())
+    jb, _ = _jobs(specs, b.data_ptr())
+    plan = r.raid6c_plan_create(ja)
+    try:
+        r.raid6c_plan_set_schedule(plan, 8, 4, 0, 1)       # grouped schedule
+        r.raid6c_plan_run(plan)
+        info = r.raid6c_plan_stats(plan)
+    finally:
+        torch.cuda.synchronize()
+        r.raid6c_plan_destroy(plan)
+    r.raid6c_run_jobs_noalloc(jb)
+    torch.cuda.synchronize()
+    log(f"{len(specs)} jobs, {total} bytes, {info.nitems} plan tiles")
+    assert not torch.equal(a, src)                        # the jobs wrote something
+    assert torch.equal(a, b)
+
+
+def test_noalloc_matches_plan_on_two_calls_second_smaller():
+    device()
+    _compare_once(_specs(71, 1500, 12288), 71)
+    _compare_once(_specs(72, 40, 2048), 72)
+
+
+def test_noalloc_refuses_beyond_its_limits():
+    import torch
+    device()
+    buf = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda:0")
+    base = buf.data_ptr()
+    one = r.raid6c_job(r.RAID6C_JOB_ENCODE, 5, 2, -1, -1, 64, 256, base)
+    with pytest.raises(r.Raid6cError) as ex:
+        r.raid6c_run_jobs_noalloc([one] * (r.RAID6C_NOALLOC_MAX_JOBS + 1))
+    assert ex.value.code == r.RAID6C_E_ARG
+    # 4096 jobs of 64 KiB rows at p = 53 (256 tiles each): over the tile limit.
+    big = r.raid6c_job(r.RAID6C_JOB_ENCODE, 53, 2, -1, -1, 65536, 52 * 65536, base)
+    with pytest.raises(r.Raid6cError) as ex:
+        r.raid6c_run_jobs_noalloc([big] * 2048)
+    assert ex.value.code == r.RAID6C_E_ARG
+    torch.cuda.synchronize()
+    assert int(buf.count_nonzero()) == 0                  # nothing was launched
