@@ -637,7 +637,8 @@ def batched_mixed(reps, stream):
         plan_ms = time_launches(lambda: r.raid6c_plan_run(plan), reps, stream)
         # Both execution modes on their own, for the record.
         modes = {}
-        for name, cand in (("grouped", (8, 4, 0, 1)), ("persistent", (8, 4, 0, 0))):
+        for name, cand in (("grouped_chained", (8, 4, 0, 2)), ("grouped_side_by_side", (8, 4, 0, 1)),
+                           ("persistent", (8, 4, 0, 0))):
             r.raid6c_plan_set_schedule(plan, *cand)
             ms_m = time_launches(lambda: r.raid6c_plan_run(plan), max(3, reps // 2), stream)
             modes[name] = round(sum(ms_m) / len(ms_m), 3)
@@ -702,18 +703,85 @@ ROWS_PROBE_CMDS = {c: f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pr
                       "-o run -- python -u bench.py --rows-probe" for c in ("FETCH_SIZE", "WRITE_SIZE")}
 
 
-def plan_jobs_bytes():
-    """Per prime: the algorithmic bytes (k+2)(p-1)W of the plan workload."""
+PLAN_PMC_CMDS = {c: f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/prof_plan_{c.split('_')[0].lower()} "
+                    "-o run -- python -u bench.py --plan-profile 3 --copy-probe" for c in ("FETCH_SIZE", "WRITE_SIZE")}
+
+
+def plan_jobs_bytes(split=False):
+    """Per prime: the algorithmic bytes (k+2)(p-1)W of the plan workload; with
+    `split`, (read, written) = (k(p-1)W, 2(p-1)W) per prime (an encode reads
+    the k data strips and writes P, Q; a two-erasure recovery reads the k
+    surviving strips and writes the 2 erased ones)."""
     import datagen
     out = {}
     for j in datagen.batch_jobs(PLAN_SEED, PLAN_STRIPES):
-        out[j.p] = out.get(j.p, 0) + (j.k + 2) * (j.p - 1) * j.row_bytes
+        strip = (j.p - 1) * j.row_bytes
+        if split:
+            rd, wr = out.get(j.p, (0, 0))
+            out[j.p] = (rd + j.k * strip, wr + 2 * strip)
+        else:
+            out[j.p] = out.get(j.p, 0) + (j.k + 2) * strip
     return out
 
 
+def summarize_plan_counters(fetch_dir: str, write_dir: str, out_dir: str = None) -> dict:
+    """HBM bytes per run of each prime's job-list grid in the PLAN_PMC_CMDS runs
+    against the bytes its jobs read and write (host-only)."""
+    import re
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    alg = plan_jobs_bytes(split=True)
+
+    def read(d, counter):
+        per, copies = {}, []
+        for r_ in _read_csv(os.path.join(d, "run_counter_collection.csv")):
+            if r_["Counter_Name"] != counter:
+                continue
+            v = float(r_["Counter_Value"])
+            if "copyBuffer" in r_["Kernel_Name"]:
+                if v > 100000:
+                    copies.append(v)
+                continue
+            m = re.search(r"zp_group_kernel<(\d+)>", r_["Kernel_Name"])
+            if m:
+                per.setdefault(int(m.group(1)), []).append((int(r_["Dispatch_Id"]), v))
+        if not copies or set(per) != set(alg):
+            raise RuntimeError(f"{d}: expected the grids of primes {sorted(alg)} and the probe copies")
+        scale = 2**30 / (sum(copies) / len(copies) * 1024)
+        # the first run warms up; average the others
+        return {p: sum(v for _, v in sorted(x)[1:]) / max(1, len(x) - 1) * 1024 * scale for p, x in per.items()}, scale
+
+    fetch, fs = read(fetch_dir, "FETCH_SIZE")
+    write, ws = read(write_dir, "WRITE_SIZE")
+    lines = ["# rocprofv3 HBM byte counters: plan of 20,000 mixed stripes (p from {5,11,13,19,29,37,53},",
+             "# k uniform in [2, p-1], rows log-uniform over 512 B..64 KiB rounded to 16 B, 60% encode / 40%",
+             "# two-erasure recovery; 7 in 8 jobs have rows off 128-byte lines), default schedule",
+             "# commands (one counter per run, from the repository root, on one MI355X):",
+             "#   " + PLAN_PMC_CMDS["FETCH_SIZE"], "#   " + PLAN_PMC_CMDS["WRITE_SIZE"],
+             f"# counters scaled by 1 GiB probe copies in the same runs: fetch x{fs:.4f}, write x{ws:.4f};",
+             "# per prime: the mean over the runs after the first; read / written = the bytes the jobs must",
+             "# read (k surviving or data strips) and write (2 strips)", "",
+             f"{'grid':<22}{'read_B':>14}{'fetched_B':>14}{'fetch/read':>11}{'written_B':>13}{'wrote_B':>13}{'ratio':>8}"]
+    table = {}
+    trd = twr = tf = tw = 0
+    for p in sorted(alg, reverse=True):
+        rd, wr = alg[p]
+        f, w = fetch[p], write[p]
+        trd, twr, tf, tw = trd + rd, twr + wr, tf + f, tw + w
+        lines.append(f"{'zp_group_kernel<%d>' % p:<22}{rd:>14}{f:>14.0f}{f / rd:>11.4f}{wr:>13}{w:>13.0f}{w / wr:>8.4f}")
+        table[p] = {"fetch_over_read": round(f / rd, 4), "write_over_written": round(w / wr, 4)}
+    lines.append(f"{'all':<22}{trd:>14}{tf:>14.0f}{tf / trd:>11.4f}{twr:>13}{tw:>13.0f}{tw / twr:>8.4f}")
+    lines.append(f"\nHBM bytes per run: {tf + tw:.0f} against {trd + twr} algorithmic ({(tf + tw) / (trd + twr):.4f}x)")
+    table["all"] = {"fetch_over_read": round(tf / trd, 4), "write_over_written": round(tw / twr, 4),
+                    "hbm_over_algorithmic": round((tf + tw) / (trd + twr), 4)}
+    with open(os.path.join(out_dir, "zp_group_kernel_plan_mixed_x20000_hbm_bytes.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return table
+
+
 def plan_profile(runs):
-    """Run the 20,000-stripe plan `runs` times under the grouped schedule
-    (nothing else is launched but the input fill), for the profiler."""
+    """Run the 20,000-stripe plan `runs` times under the default schedule
+    (per-prime job-list grids one after another; nothing else is launched but
+    the input fill), for the profiler."""
     import torch
 
     import datagen
@@ -732,7 +800,7 @@ def plan_profile(runs):
         cj.append(r.raid6c_job(op, j.p, j.k, j.e0, j.e1, j.row_bytes, (j.p - 1) * j.row_bytes, base + off))
     plan = r.raid6c_plan_create((r.raid6c_job * len(cj))(*cj))
     try:
-        r.raid6c_plan_set_schedule(plan, 8, 4, 0, 1)
+        r.raid6c_plan_set_schedule(plan, 8, 4, 0, 2)
         ms = time_launches(lambda: r.raid6c_plan_run(plan), runs, torch.cuda.current_stream())
     finally:
         r.raid6c_plan_destroy(plan)
@@ -943,14 +1011,14 @@ def summarize_plan_profile(stats_dir: str, out_dir: str = None) -> dict:
     span = sum(spans) / len(spans)
     lines = ["# rocprofv3 kernel trace: plan of 20,000 mixed stripes (p from {5,11,13,19,29,37,53},",
              "# k uniform in [2, p-1], rows log-uniform over 512 B..64 KiB, 60% encode / 40% two-erasure",
-             "# recovery), grouped schedule: one job-list grid per prime, the grids side by side in one graph",
+             "# recovery), default schedule: one job-list grid per prime, chained in one graph (one after another)",
              "# command (from the repository root, on one MI355X):", "#   " + PLAN_PROFILE_CMD,
              "# source: run_kernel_trace.csv; algorithmic bytes (k+2)(p-1)W summed over the stripes", "",
              f"plan runs timed: {len(spans)} (after one warm-up run)",
              f"span per run (first grid start to last grid end): {span / 1e6:.3f} ms",
              f"algorithmic bytes per run: {total} B -> {total / span:.1f} GB/s = "
              f"{total / span / HBM_PEAK_GBPS:.4f} of the 8 TB/s HBM peak", "",
-             "per-prime grids (they overlap in time, so a grid's duration is not its share of the run):",
+             "per-prime grids (chained: each grid runs alone, so its duration is its share of the run):",
              f"{'kernel':<24}{'avg_ns':>11}{'alg_bytes':>14}"]
     table = {"span_ns": round(span), "alg_bytes": total, "frac": round(total / span / HBM_PEAK_GBPS, 4)}
     for p in sorted(alg, reverse=True):
@@ -1102,6 +1170,8 @@ def main():
                     help="write the profiles/ summaries from the three rocprofv3 runs (no GPU needed)")
     ap.add_argument("--plan-profile", type=int, metavar="RUNS",
                     help="only run the 20,000-stripe plan RUNS times (for the profiler)")
+    ap.add_argument("--summarize-plan-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ HBM-byte summary of the two plan counter runs (no GPU needed)")
     ap.add_argument("--summarize-plan", metavar="STATS_DIR",
                     help="write the profiles/ summary of a --plan-profile run (no GPU needed)")
     ap.add_argument("--p29-profile", action="store_true",
@@ -1117,6 +1187,9 @@ def main():
     args = ap.parse_args()
     if args.summarize:
         print(json.dumps(summarize_profiles(*args.summarize), indent=1))
+        return
+    if args.summarize_plan_counters:
+        print(json.dumps(summarize_plan_counters(*args.summarize_plan_counters), indent=1))
         return
     if args.summarize_plan:
         print(json.dumps(summarize_plan_profile(args.summarize_plan), indent=1))
@@ -1152,7 +1225,10 @@ def main():
     r.load()
     stream = torch.cuda.current_stream()
     if args.plan_profile:
-        print(json.dumps(plan_profile(args.plan_profile)), flush=True)
+        res = plan_profile(args.plan_profile)
+        if args.copy_probe:
+            copy_probe(stream)
+        print(json.dumps(res), flush=True)
         return
     if args.p29_profile:
         from paper_cs_0611109_amd import autotune as at
@@ -1253,11 +1329,11 @@ def main():
         "roofline": roofline,
         "autotune": tuned,
     }
-    log(f"recovery at p={P3} k={K3} W={W3} x {N3} stripes, by erasure class")
-    result["recover_config3"] = config3(max(20, args.steps), stream)
-    log("launch latency at p=5 k=4 W=64 x 1024 stripes")
-    result["latency_config1"] = config1_latency(50, stream)
     if not args.no_extras:
+        log(f"recovery at p={P3} k={K3} W={W3} x {N3} stripes, by erasure class")
+        result["recover_config3"] = config3(max(20, args.steps), stream)
+        log("launch latency at p=5 k=4 W=64 x 1024 stripes")
+        result["latency_config1"] = config1_latency(50, stream)
         log("extras: GF(256) RS comparison, extended parity, small writes, Z17 layout, plans, server")
         result["extras"] = extras(max(10, args.steps // 2), stream)
     if not args.no_cpu_baseline:

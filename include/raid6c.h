@@ -267,14 +267,17 @@ int raid6c_rs_recover_n(int k, size_t strip_bytes, void* base,
 int raid6c_rs_set_config(int vec, int unroll, int threads);
 
 /* ------------------------------------------------------------------------
- * Plans: many stripes of mixed p, k and row size in one persistent launch
+ * Plans: many stripes of mixed p, k and row size in one graph launch
  *
  * A plan is built once from a job list and replayed any number of times.
- * Each replay is one HIP graph launch holding a single persistent kernel
- * (plus a one-thread kernel that resets its work counter): every stripe's
- * columns are cut into 256-byte work items that single-wave work-groups take
- * from a device counter, largest stripes first.  The per-stripe math is that
- * of raid6c_encode / raid6c_recover_1 / raid6c_recover_2, bit for bit.
+ * Each replay is one HIP graph launch.  With the default (grouped) schedules
+ * the graph holds one grid per prime present: a job-list kernel compiled for
+ * that prime, whose waves each take one column tile of one stripe.  With the
+ * persistent schedule it holds a single persistent kernel for all primes
+ * (plus a one-thread kernel that resets its work counter), whose single-wave
+ * work-groups take 256-byte column tiles from a device counter.  The
+ * per-stripe math is that of raid6c_encode / raid6c_recover_1 /
+ * raid6c_recover_2, bit for bit, under every schedule.
  * ------------------------------------------------------------------------ */
 
 #define RAID6C_JOB_ENCODE   0  /* write P and Q from the data strips */
@@ -300,11 +303,13 @@ typedef struct raid6c_job {
 #define RAID6C_ORDER_SUBMITTED     2  /* job order as given */
 
 /* Schedule of a plan.  Changes speed only.
- *  grouped = 1 (the default): the jobs of each prime run as one grid of a
+ *  grouped = 1: the jobs of each prime run as one grid of a
  *    job-list kernel compiled for that prime (tiles of 64 lanes x 2 dwords
- *    for p <= 29, x 1 dword above; 4 waves per work-group, one tile each);
- *    the grids are independent nodes of the plan's graph.  The other fields
- *    are kept but unused.
+ *    up to p = 53, x 1 dword above; 4 waves per work-group, one tile each);
+ *    the grids are independent nodes of the plan's graph and may run side
+ *    by side.  The other fields are kept but unused.
+ *  grouped = 2 (the default): the same grids, chained in the graph so that
+ *    they run one after another, largest prime first.
  *  grouped = 0: one persistent kernel for all primes; waves_per_cu
  *    persistent work-groups per compute unit take `chunk` 256-byte tiles per
  *    increment of a device counter, in `order`. */
@@ -312,7 +317,7 @@ typedef struct raid6c_schedule {
   int32_t waves_per_cu;  /* 1..32 */
   int32_t chunk;         /* 1..1024 */
   int32_t order;         /* RAID6C_ORDER_* */
-  int32_t grouped;       /* 0 or 1 */
+  int32_t grouped;       /* 0, 1 or 2 */
 } raid6c_schedule;
 
 typedef struct raid6c_plan_info {
@@ -349,8 +354,9 @@ int raid6c_plan_set_schedule(raid6c_plan* plan, const raid6c_schedule* schedule)
 /* Sizes of the plan.  Errors: RAID6C_E_ARG for NULL arguments. */
 int raid6c_plan_stats(const raid6c_plan* plan, raid6c_plan_info* out);
 
-/* Autotuner: time every candidate schedule (grouped, and the persistent
- * kernel with waves per CU x chunk x order)
+/* Autotuner: time every candidate schedule (grouped side by side, grouped
+ * one after another, and the persistent kernel with waves per CU x chunk x
+ * order)
  * over `reps` runs each on `stream`, keep the fastest, and return its mean
  * time per run in *best_ms (may be NULL).  Runs the plan (reps+1) times per
  * candidate, which rewrites the same output bytes.  Synchronises.

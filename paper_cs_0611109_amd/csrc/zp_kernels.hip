@@ -124,16 +124,22 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 // streaming pass for every case).  Jobs whose rows are not all on 128-byte lines load
 // with the ordinary cache policy (the lines at tile edges are read by two
 // waves); the others stream non-temporally.
-// (Vec 2 only up to p = 31: above, four strips per batch at vec 2 do not fit
-// in the registers.)
-constexpr int kGroupVec = (kVecMask & 2) && kP <= 31 ? 2 : 1;
-// Strips loaded per batch: four (measured on a mix of 20,000 stripes over
-// seven primes: 2% faster than one or two, without spills up to p = 61).
-#ifdef RAID6C_GROUP_UNROLL
+// Vector width and strips per load batch, per prime: vec 2 (tiles of 512
+// bytes) with four strips per batch up to p = 31; vec 2 with one strip per
+// batch for 37..53 (alone on a 20,000-stripe mix, the p = 37 and 53 grids
+// went from 67% to 72% of peak against vec 1 with four; two strips per batch
+// measured the same); vec 1 with four above, where vec 2 spills.
+#if defined(RAID6C_GROUP_VEC)
+constexpr int kGroupVec = RAID6C_GROUP_VEC;
+#else
+constexpr int kGroupVec = kP <= 53 ? 2 : 1;
+#endif
+#if defined(RAID6C_GROUP_UNROLL)
 constexpr int kGroupUnroll = RAID6C_GROUP_UNROLL;
 #else
-constexpr int kGroupUnroll = 4;
+constexpr int kGroupUnroll = (kP > 31 && kP <= 53) ? 1 : 4;
 #endif
+static_assert((kVecMask & kGroupVec) != 0, "job-list vector width not built");
 
 // A template on P only so that profiles name each prime's grid.
 template <int P>

@@ -104,7 +104,7 @@ def test_plan_mixed_geometries():
 
 def test_plan_every_schedule():
     specs = _mixed_jobs(2, 60)
-    scheds = [(w, c, o) for o in (0, 1, 2) for w in (1, 8) for c in (1, 5, 64)] + [(8, 4, 0, 1)]
+    scheds = [(w, c, o) for o in (0, 1, 2) for w in (1, 8) for c in (1, 5, 64)] + [(8, 4, 0, 1), (8, 4, 0, 2)]
     _run_plan(specs, seed=22, schedules=scheds)
 
 

@@ -79,18 +79,22 @@ def test_noalloc_matches_plan_on_two_calls_second_smaller():
 
 
 def test_noalloc_refuses_beyond_its_limits():
+    """Every job below lies inside `buf` (the jobs of one call share it), so
+    that even a call that were wrongly accepted would stay in bounds."""
     import torch
     device()
     buf = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda:0")
     base = buf.data_ptr()
-    one = r.raid6c_job(r.RAID6C_JOB_ENCODE, 5, 2, -1, -1, 64, 256, base)
+    one = r.raid6c_job(r.RAID6C_JOB_ENCODE, 5, 2, -1, -1, 64, 256, base)          # 1 KiB stripe
     with pytest.raises(r.Raid6cError) as ex:
         r.raid6c_run_jobs_noalloc([one] * (r.RAID6C_NOALLOC_MAX_JOBS + 1))
     assert ex.value.code == r.RAID6C_E_ARG
-    # 4096 jobs of 64 KiB rows at p = 53 (256 tiles each): over the tile limit.
-    big = r.raid6c_job(r.RAID6C_JOB_ENCODE, 53, 2, -1, -1, 65536, 52 * 65536, base)
+    # p = 3, 64 KiB rows: 3 strips of 128 KiB (384 KiB), at least 128 column
+    # tiles each; 3000 of them exceed the tile limit.
+    wide = r.raid6c_job(r.RAID6C_JOB_ENCODE, 3, 1, -1, -1, 65536, 2 * 65536, base)
+    assert 3000 * 128 > r.RAID6C_NOALLOC_MAX_ITEMS
     with pytest.raises(r.Raid6cError) as ex:
-        r.raid6c_run_jobs_noalloc([big] * 2048)
+        r.raid6c_run_jobs_noalloc([wide] * 3000)
     assert ex.value.code == r.RAID6C_E_ARG
     torch.cuda.synchronize()
     assert int(buf.count_nonzero()) == 0                  # nothing was launched
