@@ -144,8 +144,10 @@ struct raid6c_plan {
   // Grouped schedule: one job-list grid per prime, as independent graph nodes.
   struct Group {
     int p;
+    bool ext;                     // jobs with the extended Q parity (k > p)
     uint32_t first, n;            // range in gitems
   };
+  bool has_ext = false;           // some job has k > p: grouped schedules only
   std::vector<BatchItem> gitems;  // per prime, tiles of 64 lanes x that prime's group_vec dwords
   std::vector<Group> groups;
   std::vector<GroupArgs> gargs;
@@ -181,22 +183,25 @@ void order_items(raid6c_plan* pl, int order) {
   }
 }
 
-// Items of the grouped schedule: jobs of one prime together (largest p first,
-// costliest stripes first within a prime), each job's tiles consecutive.
+// Items of the grouped schedule: jobs of one prime, and of one code (plain,
+// or extended Q parity), together (largest p first, plain before extended,
+// costliest stripes first within a group), each job's tiles consecutive.
 void group_items(raid6c_plan* pl) {
   const size_t nj = pl->jobs.size();
   std::vector<uint32_t> idx(nj);
   for (size_t i = 0; i < nj; ++i) idx[i] = (uint32_t)i;
+  auto ext = [&](uint32_t j) { return pl->jobs[j].k > pl->jobs[j].p; };
   std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
     if (pl->jobs[a].p != pl->jobs[b].p) return pl->jobs[a].p > pl->jobs[b].p;
+    if (ext(a) != ext(b)) return !ext(a);
     return pl->job_cost[a] > pl->job_cost[b];
   });
   pl->gitems.clear();
   pl->groups.clear();
   for (uint32_t j : idx) {
     const int p = pl->jobs[j].p;
-    if (pl->groups.empty() || pl->groups.back().p != p)
-      pl->groups.push_back(raid6c_plan::Group{p, (uint32_t)pl->gitems.size(), 0});
+    if (pl->groups.empty() || pl->groups.back().p != p || pl->groups.back().ext != ext(j))
+      pl->groups.push_back(raid6c_plan::Group{p, ext(j), (uint32_t)pl->gitems.size(), 0});
     const uint32_t tile = 64u * 4u * (uint32_t)zp_prime_entry(p)->group_vec;
     const uint32_t w = pl->jobs[j].row_bytes;
     for (uint32_t c = 0; c < w; c += tile) pl->gitems.push_back(BatchItem{j, c});
@@ -231,7 +236,7 @@ int build_graph(raid6c_plan* pl) {
       void* params[] = {(void*)&pl->gargs[gi]};
       hipKernelNodeParams kp{};
       const ZpPrimeEntry* pe = zp_prime_entry(g.p);
-      kp.func = (void*)pe->group_kernel;
+      kp.func = (void*)(g.ext ? pe->group_ext_kernel : pe->group_kernel);
       kp.gridDim = dim3((g.n + pe->group_per_wg - 1) / pe->group_per_wg);
       kp.blockDim = dim3(pe->group_threads);
       kp.sharedMemBytes = (unsigned)pe->group_lds;
@@ -280,9 +285,10 @@ int raid6c::check_job(const raid6c_job& J, size_t i, Case* out) {
   const int p = J.p, k = J.k;
   if (!is_odd_prime(p)) return fail(RAID6C_E_ARG, "job %zu: p = %d is not an odd prime", i, p);
   if (p > kMaxPrime) return fail(RAID6C_E_UNSUPPORTED, "job %zu: p = %d is not built", i, p);
-  if (k > p && k < 2 * p)
-    return fail(RAID6C_E_UNSUPPORTED, "job %zu: k = %d > p: plans run the plain code only (k <= p)", i, k);
-  if (k < 1 || k > p) return fail(RAID6C_E_ARG, "job %zu: k = %d not in [1, %d]", i, k, p);
+  const int kmax = raid6c_max_data_strips(p);
+  if (k < 1 || k > kmax)
+    return fail(RAID6C_E_ARG, "job %zu: k = %d not in [1, %d]%s", i, k, kmax,
+                kmax == p ? " (p fails Theorem 3.3.3: no extended Q parity)" : "");
   if (J.row_bytes == 0 || (J.row_bytes % 16) != 0)
     return fail(RAID6C_E_ARG, "job %zu: row_bytes must be a positive multiple of 16", i);
   if ((uint64_t)(p - 1) * J.row_bytes >= (1ull << 31)) return fail(RAID6C_E_ARG, "job %zu: strip of 2 GiB or more", i);
@@ -355,6 +361,7 @@ int raid6c_plan_create(const raid6c_job* jobs, size_t njobs, raid6c_plan** out) 
       return rc;
     }
     pl->jobs.push_back(make_batch_job(J, cs));
+    if (k > p) pl->has_ext = true;
     const uint64_t strip = (uint64_t)(p - 1) * J.row_bytes;
     const int moved = (cs.op == OP_P || cs.op == OP_Q || cs.op == OP_D) ? k + 1 : k + 2;
     pl->bytes += (uint64_t)moved * strip;
@@ -446,6 +453,8 @@ int raid6c_plan_get_schedule(const raid6c_plan* plan, raid6c_schedule* out) {
 int raid6c_plan_set_schedule(raid6c_plan* plan, const raid6c_schedule* s) {
   if (plan == nullptr || s == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
   if (!valid_schedule(*s)) return fail(RAID6C_E_ARG, "invalid schedule");
+  if (s->grouped == 0 && plan->has_ext)
+    return fail(RAID6C_E_UNSUPPORTED, "the persistent kernel runs the plain code only (a job has k > p)");
   const bool reorder = s->order != plan->sched.order;
   // A persistent-kernel replay reads the item order from device memory:
   // finish the runs in flight before it is rewritten.
@@ -488,8 +497,10 @@ int raid6c_plan_autotune(raid6c_plan* plan, void* stream, int reps, float* best_
   raid6c_schedule best = plan->sched;
   float best_t = 1e30f;
   int rc = RAID6C_OK;
-  // The two grouped schedules, then every persistent-kernel candidate.
-  for (int gi = 0; gi < 2 + 2 * 4 * 3; ++gi) {
+  // The two grouped schedules, then every persistent-kernel candidate (plain
+  // code only).
+  const int ncand = plan->has_ext ? 2 : 2 + 2 * 4 * 3;
+  for (int gi = 0; gi < ncand; ++gi) {
     {
       {
         const raid6c_schedule cand = gi < 2 ? raid6c_schedule{8, 4, RAID6C_ORDER_LARGEST_FIRST, 1 + gi}

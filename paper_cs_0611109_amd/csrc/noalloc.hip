@@ -63,9 +63,10 @@ extern "C" int raid6c_run_jobs_noalloc(const raid6c_job* jobs, size_t njobs, voi
   if (jobs == nullptr && njobs != 0) return fail(RAID6C_E_ARG, "jobs is NULL");
   if (njobs > kNoAllocJobs)
     return fail(RAID6C_E_ARG, "%zu jobs: at most %zu without allocation", njobs, kNoAllocJobs);
-  // Checks, and the items of each prime: tiles of 64 lanes x that prime's
-  // job-list vector width, jobs in the order given.
-  size_t per_prime[kMaxPrime + 1] = {};
+  // Checks, and the items of each group (prime, and plain or extended Q
+  // parity): tiles of 64 lanes x that prime's job-list vector width, jobs in
+  // the order given.
+  size_t per_group[2][kMaxPrime + 1] = {};
   size_t nitems = 0;
   for (size_t i = 0; i < njobs; ++i) {
     Case cs;
@@ -73,7 +74,7 @@ extern "C" int raid6c_run_jobs_noalloc(const raid6c_job* jobs, size_t njobs, voi
     if (rc != RAID6C_OK) return rc;
     const uint32_t tile = 64u * 4u * (uint32_t)zp_prime_entry(jobs[i].p)->group_vec;
     const size_t n = (jobs[i].row_bytes + tile - 1) / tile;
-    per_prime[jobs[i].p] += n;
+    per_group[jobs[i].k > jobs[i].p][jobs[i].p] += n;
     nitems += n;
   }
   if (nitems > kNoAllocItems)
@@ -90,23 +91,25 @@ extern "C" int raid6c_run_jobs_noalloc(const raid6c_job* jobs, size_t njobs, voi
   const int rc = scratch_on(dev, &d_scratch);
   if (rc != RAID6C_OK) return rc;
 
-  // Items grouped by prime, largest prime first (as a plan's grouped
-  // schedule orders them); first[p] is where prime p's items start.
-  size_t first[kMaxPrime + 1] = {};
+  // Items grouped by prime, largest prime first, plain before extended (as a
+  // plan's grouped schedule orders them); first[x][p] is where group (p, x)
+  // starts.
+  size_t first[2][kMaxPrime + 1] = {};
   size_t pos = 0;
-  for (int p = kMaxPrime; p >= 3; --p) {
-    first[p] = pos;
-    pos += per_prime[p];
-  }
-  size_t fill[kMaxPrime + 1];
+  for (int p = kMaxPrime; p >= 3; --p)
+    for (int x = 0; x < 2; ++x) {
+      first[x][p] = pos;
+      pos += per_group[x][p];
+    }
+  size_t fill[2][kMaxPrime + 1];
   memcpy(fill, first, sizeof fill);
   for (size_t i = 0; i < njobs; ++i) {
     Case cs;
     (void)check_job(jobs[i], i, &cs);
     g_jobs[i] = make_batch_job(jobs[i], cs);
-    const int p = jobs[i].p;
+    const int p = jobs[i].p, x = jobs[i].k > p;
     const uint32_t tile = 64u * 4u * (uint32_t)zp_prime_entry(p)->group_vec;
-    for (uint32_t c = 0; c < jobs[i].row_bytes; c += tile) g_items[fill[p]++] = BatchItem{(uint32_t)i, c};
+    for (uint32_t c = 0; c < jobs[i].row_bytes; c += tile) g_items[fill[x][p]++] = BatchItem{(uint32_t)i, c};
   }
 
   const hipStream_t s = (hipStream_t)stream;
@@ -115,14 +118,17 @@ extern "C" int raid6c_run_jobs_noalloc(const raid6c_job* jobs, size_t njobs, voi
   if ((e = hipMemcpyAsync((void*)d_jobs, g_jobs, njobs * sizeof(BatchJob), hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync((void*)d_items, g_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail(RAID6C_E_HIP, "table upload: %s", hipGetErrorString(e));
-  for (int p = kMaxPrime; p >= 3; --p) {
-    if (per_prime[p] == 0) continue;
-    const ZpPrimeEntry* pe = zp_prime_entry(p);
-    GroupArgs ga{d_jobs, d_items + first[p], (uint32_t)per_prime[p]};
-    void* args[] = {(void*)&ga};
-    const unsigned grid = (unsigned)((per_prime[p] + pe->group_per_wg - 1) / pe->group_per_wg);
-    e = hipLaunchKernel(pe->group_kernel, dim3(grid), dim3(pe->group_threads), args, (size_t)pe->group_lds, s);
-    if (e != hipSuccess) return fail(RAID6C_E_HIP, "job-list launch (p = %d): %s", p, hipGetErrorString(e));
-  }
+  for (int p = kMaxPrime; p >= 3; --p)
+    for (int x = 0; x < 2; ++x) {
+      const size_t n = per_group[x][p];
+      if (n == 0) continue;
+      const ZpPrimeEntry* pe = zp_prime_entry(p);
+      GroupArgs ga{d_jobs, d_items + first[x][p], (uint32_t)n};
+      void* args[] = {(void*)&ga};
+      const unsigned grid = (unsigned)((n + pe->group_per_wg - 1) / pe->group_per_wg);
+      e = hipLaunchKernel(x ? pe->group_ext_kernel : pe->group_kernel, dim3(grid), dim3(pe->group_threads), args,
+                          (size_t)pe->group_lds, s);
+      if (e != hipSuccess) return fail(RAID6C_E_HIP, "job-list launch (p = %d): %s", p, hipGetErrorString(e));
+    }
   return RAID6C_OK;
 }

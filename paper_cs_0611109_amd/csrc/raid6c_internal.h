@@ -86,7 +86,7 @@ struct ZpConfig {
 
 enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
 
-// Per-prime launchers, three translation units per prime (zp_kernels.hip).
+// Per-prime launchers, five translation units per prime (zp_kernels.hip).
 // Return hipSuccess or the launch error (hipErrorInvalidValue for a
 // configuration that is not built).
 typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a,
@@ -117,6 +117,13 @@ struct ZpPrimeEntry {
   int group_per_wg;
   int group_threads;
   int group_lds;
+  // The same kernel for jobs with the extended Q parity (k > p): same
+  // launch shape; group_ext_vec equals group_vec.
+  const void* group_ext_kernel;
+  int group_ext_vec;
+
+  // Job-list kernel for jobs with k data strips.
+  const void* group_fn(int k) const { return k > p ? group_ext_kernel : group_kernel; }
 
   bool has(int vec, int unroll) const {
     return (vec == 1 || vec == 2 || vec == 4) && (vec_mask & vec) &&

@@ -133,7 +133,8 @@ uint64_t stripe_bytes(int p, int k, uint32_t w) { return round_up((uint64_t)(k +
 int check_request(const raid6c_request& r) {
   if (r.kind != RAID6C_REQ_WRITE && r.kind != RAID6C_REQ_READ) return RAID6C_ST_INVALID;
   if (r.kind == RAID6C_REQ_READ) return RAID6C_ST_OK;  // geometry comes from the stripe
-  if (!is_odd_prime(r.p) || r.p > kMaxPrime || r.k < 1 || r.k > r.p) return RAID6C_ST_INVALID;
+  if (!is_odd_prime(r.p) || r.p > kMaxPrime || r.k < 1 || r.k > raid6c_max_data_strips(r.p))
+    return RAID6C_ST_INVALID;
   if (r.row_bytes == 0 || (r.row_bytes % 16) != 0) return RAID6C_ST_INVALID;
   if ((uint64_t)(r.p - 1) * r.row_bytes >= (1ull << 31)) return RAID6C_ST_INVALID;
   if (r.src == nullptr || ((uintptr_t)r.src & 15u) != 0) return RAID6C_ST_INVALID;
@@ -281,50 +282,57 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
   const BatchJob* d_jobs = (const BatchJob*)(d_tab + jobs_off);
   const BatchItem* d_items = (const BatchItem*)d_tab;
   hipError_t e;
-  if (!s->cfg.persistent) {
-    // One grid of each prime's job-list kernel (as in a plan's grouped
-    // schedule): requests by prime, largest first; items are that prime's
-    // tiles (at least kBatchTileBytes, so the table holds them).
-    std::vector<uint32_t> order(sl.reqs.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (uint32_t)i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t x, uint32_t y) { return sl.reqs[x].stripe->p > sl.reqs[y].stripe->p; });
-    struct Group {
-      const ZpPrimeEntry* pe;
-      uint32_t first, n;
-    };
-    std::vector<Group> groups;
-    nitems = 0;
-    for (uint32_t i : order) {
-      const Resident* st = sl.reqs[i].stripe;
-      if (groups.empty() || groups.back().pe->p != st->p)
-        groups.push_back(Group{zp_prime_entry(st->p), (uint32_t)nitems, 0});
-      const uint32_t tile = 64u * 4u * (uint32_t)groups.back().pe->group_vec;
-      for (uint32_t c = 0; c < st->row_bytes; c += tile) h_items[nitems++] = BatchItem{i, c};
-      groups.back().n = (uint32_t)nitems - groups.back().first;
-    }
-    e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice,
-                       sl.stream);
-    if (e != hipSuccess) return e;
-    for (const Group& g : groups) {
-      GroupArgs ga{d_jobs, d_items + g.first, g.n};
-      void* args[] = {(void*)&ga};
-      const int per = g.pe->group_per_wg;
-      e = hipLaunchKernel(g.pe->group_kernel, dim3((g.n + per - 1) / per), dim3(g.pe->group_threads), args,
-                          (size_t)g.pe->group_lds, sl.stream);
-      if (e != hipSuccess) return e;
-    }
-    return hipEventRecord(sl.done, sl.stream);
+  // Grids of the job-list kernels (as in a plan's grouped schedule): the
+  // requests of one prime and one code (plain, or extended Q parity: k > p)
+  // form a grid, largest prime first; items are that prime's tiles (at least
+  // kBatchTileBytes, so the table holds them).  With `persistent` set, only
+  // the extended-parity requests go this way (the persistent kernel runs the
+  // plain code), and their items follow the persistent kernel's.
+  auto is_ext = [&](uint32_t i) { return sl.reqs[i].stripe->k > sl.reqs[i].stripe->p; };
+  std::vector<uint32_t> order;
+  for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
+    if (!s->cfg.persistent || is_ext(i)) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    if (sl.reqs[x].stripe->p != sl.reqs[y].stripe->p) return sl.reqs[x].stripe->p > sl.reqs[y].stripe->p;
+    return !is_ext(x) && is_ext(y);
+  });
+  struct Group {
+    const ZpPrimeEntry* pe;
+    bool ext;
+    uint32_t first, n;
+  };
+  std::vector<Group> groups;
+  size_t pitems = 0;  // the persistent kernel's items, first in the table
+  if (s->cfg.persistent) {
+    // 256-byte tiles of the plain-code requests, in request order.
+    for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
+      if (!is_ext(i))
+        for (uint32_t c = 0; c < sl.reqs[i].stripe->row_bytes; c += kBatchTileBytes) h_items[pitems++] = BatchItem{i, c};
   }
-  // One persistent kernel over 256-byte tiles in request order.
-  nitems = 0;
-  for (size_t i = 0; i < sl.reqs.size(); ++i)
-    for (uint32_t c = 0; c < sl.reqs[i].stripe->row_bytes; c += kBatchTileBytes)
-      h_items[nitems++] = BatchItem{(uint32_t)i, c};
+  nitems = pitems;
+  for (uint32_t i : order) {
+    const Resident* st = sl.reqs[i].stripe;
+    if (groups.empty() || groups.back().pe->p != st->p || groups.back().ext != is_ext(i))
+      groups.push_back(Group{zp_prime_entry(st->p), is_ext(i), (uint32_t)nitems, 0});
+    const uint32_t tile = 64u * 4u * (uint32_t)groups.back().pe->group_vec;
+    for (uint32_t c = 0; c < st->row_bytes; c += tile) h_items[nitems++] = BatchItem{i, c};
+    groups.back().n = (uint32_t)nitems - groups.back().first;
+  }
   // One upload for both tables.
   e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice,
                      sl.stream);
   if (e != hipSuccess) return e;
+  for (const Group& g : groups) {
+    GroupArgs ga{d_jobs, d_items + g.first, g.n};
+    void* args[] = {(void*)&ga};
+    const int per = g.pe->group_per_wg;
+    e = hipLaunchKernel(g.ext ? g.pe->group_ext_kernel : g.pe->group_kernel, dim3((g.n + per - 1) / per),
+                        dim3(g.pe->group_threads), args, (size_t)g.pe->group_lds, sl.stream);
+    if (e != hipSuccess) return e;
+  }
+  if (!s->cfg.persistent || pitems == 0) return hipEventRecord(sl.done, sl.stream);
+  // One persistent kernel over the plain-code requests' 256-byte tiles.
+  nitems = pitems;
   int max_p = 3;
   for (const InFlight& f : sl.reqs) max_p = std::max(max_p, f.stripe->p);
   const int waves = s->cfg.waves_per_cu > 0 ? s->cfg.waves_per_cu : 8;

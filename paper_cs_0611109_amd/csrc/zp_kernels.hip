@@ -1,16 +1,17 @@
 // zp_kernels.hip -- Z_p-RAID encode and recovery kernels for one prime.
 //
-// This file is compiled three times per supported prime, with
+// This file is compiled five times per supported prime, with
 // -DRAID6C_P=<p> and -DRAID6C_VARIANT=
 //   0  the plain code (k <= p), one column slice per thread;
 //   1  the extended Q parity (p < k <= 2p-1, Section 3.3), same mapping;
 //   2  split-K, plain code and extended Q parity: the waves of a work-group
 //      share a column tile and split the data strips;
 //   3  the job-list kernel of plans: the tiles of many stripes of this prime,
-//      each with its own geometry, one per wave.
+//      each with its own geometry, one per wave;
+//   4  the same for stripes with the extended Q parity (p < k <= 2p-1).
 // Each object is compiled alone so that the code of one never shapes the
 // compiler's choices for the others; object 0 holds the dispatch entry and
-// calls into the other two.
+// calls into the others.
 //
 // Grid (variants 0, 1): one work-group per (stripe, column tile); a tile is
 // `threads` threads times V dwords of every row.  Work-group i handles stripe
@@ -117,8 +118,9 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 }
 #endif
 
-#if RAID6C_VARIANT == 3
-// Job-list kernel of plans (plain code).  Work-groups of 4 waves; wave w of
+#if RAID6C_VARIANT == 3 || RAID6C_VARIANT == 4
+// Job-list kernels of plans (variant 3: plain code; variant 4: extended Q
+// parity, k > p).  Work-groups of 4 waves; wave w of
 // work-group b takes item 4b + w: a tile of 64 lanes x GV dwords of one job
 // (any base, strip stride, row size, case), run by tile_recover_one_pass (one
 // streaming pass for every case).  Jobs whose rows are not all on 128-byte lines load
@@ -141,10 +143,9 @@ constexpr int kGroupUnroll = (kP > 31 && kP <= 53) ? 1 : 4;
 #endif
 static_assert((kVecMask & kGroupVec) != 0, "job-list vector width not built");
 
-// A template on P only so that profiles name each prime's grid.
-template <int P>
-__global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
-  extern __shared__ __align__(16) uint32_t smem[];
+// One column tile of one job, by one wave (EXT: extended Q parity).
+template <int P, bool EXT>
+__device__ __forceinline__ void group_item(const GroupArgs& a, uint32_t* smem) {
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t i = xcd_chunk(blockIdx.x, gridDim.x) * 4 + w;
@@ -157,11 +158,26 @@ __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
                   j.row_bytes, col, (uint32_t)((P - 1) * j.row_bytes)};
   const Case cs{j.op, j.x, j.y};
   if (c.lines_aligned())
-    tile_recover_one_pass<P, kGroupVec, kGroupUnroll, false>(c, j.k, cs, smem + threadIdx.x, 256);
+    tile_recover_one_pass<P, kGroupVec, kGroupUnroll, EXT>(c, j.k, cs, smem + threadIdx.x, 256);
   else
-    tile_recover_one_pass<P, kGroupVec, kGroupUnroll, false>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
-                                                             smem + threadIdx.x, 256);
+    tile_recover_one_pass<P, kGroupVec, kGroupUnroll, EXT>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
+                                                           smem + threadIdx.x, 256);
 }
+
+// Templates on P only so that profiles name each prime's grid.
+#if RAID6C_VARIANT == 3
+template <int P>
+__global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  group_item<P, false>(a, smem);
+}
+#else
+template <int P>
+__global__ void __launch_bounds__(256) zp_group_ext_kernel(const GroupArgs a) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  group_item<P, true>(a, smem);
+}
+#endif
 #endif
 
 // (vec, unroll) pairs built for this prime: accumulators take (2p-1)*vec
@@ -193,7 +209,7 @@ constexpr int unroll_mask(int v) {
 template <int V, int U, int LP>
 hipError_t launch_lp(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                      hipStream_t stream) {
-  if constexpr (built<V, U>() && RAID6C_VARIANT != 3) {
+  if constexpr (built<V, U>() && RAID6C_VARIANT < 3) {
 #if RAID6C_VARIANT == 2
     (void)kind;
     const dim3 g(grid);
@@ -257,6 +273,7 @@ hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg
 hipError_t RAID6C_CAT(zp_launch_split_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
                                                   hipStream_t stream);
 void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e);
+void RAID6C_CAT(zp_group_ext_shape_, RAID6C_P)(ZpPrimeEntry& e);
 
 #if RAID6C_VARIANT == 3
 void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e) {
@@ -265,6 +282,12 @@ void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e) {
   e.group_per_wg = 4;
   e.group_threads = 256;
   e.group_lds = kP * 256 * 4;
+}
+#elif RAID6C_VARIANT == 4
+// Same tiles and launch shape as the plain job-list kernel (same constants).
+void RAID6C_CAT(zp_group_ext_shape_, RAID6C_P)(ZpPrimeEntry& e) {
+  e.group_ext_kernel = (const void*)zp_group_ext_kernel<kP>;
+  e.group_ext_vec = kGroupVec;
 }
 #elif RAID6C_VARIANT == 1
 hipError_t RAID6C_CAT(zp_launch_ext_, RAID6C_P)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a, uint32_t grid,
@@ -288,8 +311,9 @@ ZpPrimeEntry make_entry() {
   ZpPrimeEntry e{kP, &launch_plain, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
                  {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)},
                  {0, split_mask(1), split_mask(2), 0, split_mask(4)},
-                 nullptr, 0, 0, 0, 0};
+                 nullptr, 0, 0, 0, 0, nullptr, 0};
   RAID6C_CAT(zp_group_shape_, RAID6C_P)(e);
+  RAID6C_CAT(zp_group_ext_shape_, RAID6C_P)(e);
   return e;
 }
 }  // namespace

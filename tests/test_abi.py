@@ -221,10 +221,22 @@ def test_plan_rejects_bad_jobs_before_device_work():
         _err(r.raid6c_plan_create, [bad])
         _err(r.raid6c_plan_create, [good, bad])
     _err(r.raid6c_plan_create, [J(0, 67, 4, -1, -1, 64, 66 * 64, FAKE)], code=r.RAID6C_E_UNSUPPORTED)
-    # extended Q parity (k > p) is not run by plans
-    _err(r.raid6c_plan_create, [J(0, 5, 6, -1, -1, 64, 256, FAKE)], code=r.RAID6C_E_UNSUPPORTED)
+    # k > p only where the prime has the extended Q parity (7 fails Theorem 3.3.3)
+    _err(r.raid6c_plan_create, [J(0, 7, 8, -1, -1, 64, 384, FAKE)])
     # two jobs sharing bytes
     _err(r.raid6c_plan_create, [J(0, 5, 4, -1, -1, 64, 256, FAKE), J(0, 5, 4, -1, -1, 64, 256, FAKE + 1024)])
+
+
+def test_noalloc_rejects_bad_calls_before_device_work():
+    J = r.raid6c_job
+    good = J(0, 5, 4, -1, -1, 64, 256, FAKE)
+    for bad in (J(0, 9, 4, -1, -1, 64, 256, FAKE), J(0, 5, 10, -1, -1, 64, 256, FAKE),
+                J(0, 7, 8, -1, -1, 64, 384, FAKE), J(1, 5, 4, 2, 2, 64, 256, FAKE)):
+        _err(r.raid6c_run_jobs_noalloc, [good, bad], stream=0)
+    _err(r.raid6c_run_jobs_noalloc, [good] * (r.RAID6C_NOALLOC_MAX_JOBS + 1), stream=0)
+    wide = J(0, 3, 1, -1, -1, 65536, 2 * 65536, FAKE)                   # 128 tiles of 512 bytes
+    _err(r.raid6c_run_jobs_noalloc, [wide] * (r.RAID6C_NOALLOC_MAX_ITEMS // 128 + 1), stream=0)
+    assert r.raid6c_run_jobs_noalloc([], stream=0) == 0
 
 
 def test_server_rejects_bad_configurations_before_device_work():

@@ -14,13 +14,14 @@ pytestmark = pytest.mark.gpu
 PRIMES = [3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61]
 
 
-def _mixed_jobs(seed, n, w_max=1200):
-    """Random geometries over every prime, all erasure cases, ragged rows."""
+def _mixed_jobs(seed, n, w_max=1200, ext=False):
+    """Random geometries over every prime, all erasure cases, ragged rows;
+    with `ext`, k up to 2p-1 (extended Q parity) where the prime allows it."""
     d = datagen.Draws(seed, datagen.TAG_GEOMETRY, 1)
     out = []
     for i in range(n):
         p = PRIMES[d.below(len(PRIMES))]
-        k = d.between(1, p)
+        k = d.between(1, r.raid6c_max_data_strips(p) if ext else p)
         w = 16 * d.between(1, w_max // 16)
         kind = d.below(3)
         if kind == 0:
@@ -136,3 +137,30 @@ def test_empty_plan():
     r.raid6c_plan_run(plan)
     assert r.raid6c_plan_stats(plan).nitems == 0
     r.raid6c_plan_destroy(plan)
+
+
+def test_plan_extended_q_parity_mixed_with_plain():
+    """Jobs with k up to 2p-1 (extended Q parity, Section 3.3) beside plain
+    ones, every case, both grouped schedules; the persistent kernel (plain
+    code only) is refused for such a plan."""
+    specs = _mixed_jobs(6, 120, w_max=640, ext=True)
+    n_ext = sum(k > p for p, k, _, _ in specs)
+    log(f"plan with {len(specs)} jobs, {n_ext} with k > p")
+    assert n_ext >= 30
+    _run_plan(specs, seed=26, schedules=[(8, 4, 0, 1), (8, 4, 0, 2)])
+    _run_plan(specs[:40], seed=27, autotune=True)
+
+
+def test_plan_extended_refuses_persistent_schedule():
+    import torch
+    device()
+    p, k, w = 13, 20, 64
+    buf = torch.zeros((k + 2) * (p - 1) * w, dtype=torch.uint8, device="cuda:0")
+    plan = r.raid6c_plan_create([r.raid6c_job(r.RAID6C_JOB_ENCODE, p, k, -1, -1, w, (p - 1) * w, buf.data_ptr())])
+    try:
+        with pytest.raises(r.Raid6cError) as ex:
+            r.raid6c_plan_set_schedule(plan, 8, 4, 0, 0)
+        assert ex.value.code == r.RAID6C_E_UNSUPPORTED
+        r.raid6c_plan_run(plan)
+    finally:
+        r.raid6c_plan_destroy(plan)

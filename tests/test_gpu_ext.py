@@ -127,11 +127,18 @@ def test_extended_every_launch_configuration(p):
             cfgs = [(t, 1) for t in (64, 128, 256)] + [(64 * sp, sp) for sp in (2, 4) if r.raid6c_split_mask(p, v) & sp]
             for t, sp in cfgs:
                 log(f"extended config p={p} k={k} vec={v} unroll={u} threads={t} split={sp}")
-                r.raid6c_tune_set(p, 0, w, v, u, t, sp)
-                r.raid6c_tune_set(p, 1, w, v, u, t, sp)
+                _set_ext(p, w, v, u, t, sp)
                 assert np.array_equal(_encode(want[:2], p, k, w), want[:2]), (v, u, t, sp)
                 assert np.array_equal(_recover(want, p, k, w, er), want), (v, u, t, sp)
     r.raid6c_tune_clear()
+
+
+def _set_ext(p, w, v, u, t, sp, order=0):
+    """Launch configuration of stripes with k > p (table slots 2: encode, 3:
+    recovery), checked to be the one the next launches will use."""
+    for op in (2, 3):
+        r.raid6c_tune_set(p, op, w, v, u, t, sp, order)
+        assert r.raid6c_tune_get(p, op, w) == (v, u, t, sp, order), (p, op, w)
 
 
 @pytest.mark.parametrize("p", [5, 13, 29])
@@ -151,13 +158,49 @@ def test_extended_split_every_class(p):
                 if not r.raid6c_split_mask(p, v) & sp:
                     continue
                 log(f"extended split p={p} k={k} vec={v} unroll={u} split={sp} entries={len(er)}")
-                r.raid6c_tune_set(p, 0, w, v, u, 64 * sp, sp)
-                r.raid6c_tune_set(p, 1, w, v, u, 64 * sp, sp)
+                _set_ext(p, w, v, u, 64 * sp, sp)
                 assert np.array_equal(_encode(want, p, k, w), want), (v, u, sp)
                 assert np.array_equal(_recover(want, p, k, w, er), want), (v, u, sp)
                 n += 1
     r.raid6c_tune_clear()
     assert n > 0
+
+
+def test_extended_default_rule_large_prime_whole_tiles():
+    """p = 53, k = 2p-1, rows of whole 512-byte tiles: the built-in rule's
+    choice for extended stripes (no table entry), every erasure class."""
+    p, k, w = 53, 105, 1024
+    er = _pick(p, k, 4, seed=53)
+    want = _stripes(p, k, w, len(er), seed=19 * p)
+    log(f"extended default rule p={p} k={k} W={w}: encode {r.raid6c_tune_get(p, 2, w)}, "
+        f"recovery {r.raid6c_tune_get(p, 3, w)}")
+    assert np.array_equal(_encode(want, p, k, w), want)
+    assert np.array_equal(_recover(want, p, k, w, er), want)
+
+
+def test_extended_cached_entries():
+    """Each extended-parity entry of the shipped tuning cache, at its own
+    geometry (fewer stripes), every erasure class."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(r.__file__), "tuned_mi355x.json")
+    with open(path) as f:
+        entries = [e for e in json.load(f)["entries"] if e["op"] in (2, 3)]
+    assert entries
+    for e in entries:
+        p, w, k = e["p"], e["row_bytes"], e["k"]
+        cfg = (e["vec"], e["unroll"], e["threads"], e["split"], e["order"])
+        r.raid6c_tune_clear()
+        r.raid6c_tune_set(p, e["op"], w, *cfg)
+        assert r.raid6c_tune_get(p, e["op"], w) == cfg
+        er = _pick(p, k, 3, seed=e["op"] * 100 + p)
+        want = _stripes(p, k, w, len(er), seed=23 * p + e["op"])
+        log(f"cached extended entry p={p} op={e['op']} W={w} k={k} config={cfg}")
+        if e["op"] == 2:
+            assert np.array_equal(_encode(want, p, k, w), want), cfg
+        else:
+            assert np.array_equal(_recover(want, p, k, w, er), want), cfg
+    r.raid6c_tune_clear()
 
 
 def test_extended_single_stripe_pointer_tables():

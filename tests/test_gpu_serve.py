@@ -214,6 +214,51 @@ def test_full_size_payloads_alone_and_in_the_mix_are_identical():
         assert np.array_equal(s0[k], s1[k]) and np.array_equal(s0[k], s2[k])
 
 
+def _ext_trace(seed, n):
+    """Writes of stripes with the extended Q parity (p < k <= 2p-1, Section
+    3.3) and degraded reads of them (one or two strips, at least one data
+    strip, plain or extended)."""
+    d = datagen.Draws(seed, datagen.TAG_ARRIVAL, 3)
+    out, writes, t = [], [], 0.0
+    for i in range(n):
+        t += d.exponential(20000.0)
+        if i < 8 or d.unit() < 0.5:
+            p = (5, 11, 13, 29)[d.below(4)]
+            k = d.between(p + 1, 2 * p - 1)
+            w = 16 * d.between(1, 40)
+            out.append(datagen.Request(i, t, "write", p, k, w, k * (p - 1) * w, -1, -1, -1))
+            writes.append(i)
+        else:
+            tgt = writes[d.below(len(writes))]
+            src = out[tgt]
+            k = src.k
+            e0 = d.below(k)
+            e1 = -1
+            if d.unit() < 0.5:
+                e1 = d.below(k + 1)
+                e1 += e1 >= e0
+                e0, e1 = min(e0, e1), max(e0, e1)
+            out.append(datagen.Request(i, t, "read", src.p, k, src.row_bytes, src.payload, e0, e1, tgt))
+    return out
+
+
+@pytest.mark.parametrize("mode", ["plain", "grouped", "persistent"])
+def test_extended_q_parity_requests_match_oracle(mode):
+    device()
+    reqs = _ext_trace(36, 160)
+    c, pay, out, out_off, data = _stage(reqs, 36)
+    stripes = _expected_stripes(reqs, data)
+    srv = r.raid6c_server_create(1 << 30, max_inflight=4, max_batch=16, plain=mode == "plain",
+                                 persistent=mode == "persistent")
+    try:
+        comps = r.raid6c_server_replay(srv, c, [q.arrival_s for q in reqs])
+        st = r.raid6c_server_get_stats(srv)
+        log(f"extended, {mode}: {st.batches} batches for {st.completed} requests")
+        _check(srv, reqs, comps, out, out_off, stripes)
+    finally:
+        r.raid6c_server_destroy(srv)
+
+
 def test_small_budget_evicts_oldest_and_reports_not_resident():
     device()
     reqs = _trace(33, 200, qps=5000.0)

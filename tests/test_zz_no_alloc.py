@@ -16,13 +16,13 @@ PRIMES = [3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61]
 
 
 def _specs(seed, n, w_max):
-    """Mixed geometries over every prime, every job kind, ragged rows (some
-    off 128-byte lines)."""
+    """Mixed geometries over every prime, every job kind, plain and extended
+    Q parity, ragged rows (some off 128-byte lines)."""
     d = datagen.Draws(seed, datagen.TAG_GEOMETRY, 2)
     out = []
     for _ in range(n):
         p = PRIMES[d.below(len(PRIMES))]
-        k = d.between(1, p)
+        k = d.between(1, r.raid6c_max_data_strips(p))   # extended Q parity where the prime allows
         w = 16 * d.between(1, w_max // 16)
         kind = d.below(3)
         if kind == 0:
