@@ -471,6 +471,8 @@ typedef struct raid6c_server_stats {
   uint64_t resident;     /* stripes in the store */
   uint64_t store_used;   /* bytes they occupy */
   uint64_t table_grows;  /* batches whose slot had to enlarge its job/item tables */
+  uint64_t admit_ns;     /* scheduler time spent admitting requests into batches */
+  uint64_t launch_ns;    /* scheduler time spent building tables and launching batches */
 } raid6c_server_stats;
 
 typedef struct raid6c_server raid6c_server;

@@ -111,7 +111,8 @@ class raid6c_server_config(ctypes.Structure):
 class raid6c_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("evictions", ctypes.c_uint64), ("user_bytes", ctypes.c_uint64), ("resident", ctypes.c_uint64),
-                ("store_used", ctypes.c_uint64), ("table_grows", ctypes.c_uint64)]
+                ("store_used", ctypes.c_uint64), ("table_grows", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
+                ("launch_ns", ctypes.c_uint64)]
 
 
 RAID6C_REQ_WRITE = 0

@@ -1,9 +1,10 @@
 """Build libraid6c.so in-tree with hipcc for gfx950.
 
-The Z_p kernel source is compiled five times per supported prime
-(-DRAID6C_P=p, -DRAID6C_VARIANT=0/1/2/3/4: plain, extended Q parity, split-K,
-plan job list, plan job list with extended Q parity), in parallel, then
-everything is linked into ``paper_cs_0611109_amd/libraid6c.so``.
+The Z_p kernel source is compiled six times per supported prime
+(-DRAID6C_P=p, -DRAID6C_VARIANT=0..5: plain, extended Q parity, split-K,
+plan job list, plan job list with extended Q parity, the server's job list
+for small batches), in parallel, then everything is linked into
+``paper_cs_0611109_amd/libraid6c.so``.
 """
 
 from __future__ import annotations
@@ -39,7 +40,8 @@ def _units(build_dir):
     for src in SOURCES:
         units.append((os.path.join(CSRC, src), os.path.join(build_dir, src.replace(".hip", ".o")), []))
     for p in PRIMES:
-        for variant, suffix in ((0, ""), (1, "_ext"), (2, "_split"), (3, "_group"), (4, "_group_ext")):
+        for variant, suffix in ((0, ""), (1, "_ext"), (2, "_split"), (3, "_group"), (4, "_group_ext"),
+                                (5, "_group_lat")):
             units.append((os.path.join(CSRC, "zp_kernels.hip"),
                           os.path.join(build_dir, f"zp_kernels_p{p}{suffix}.o"),
                           [f"-DRAID6C_P={p}", f"-DRAID6C_VARIANT={variant}"]))

@@ -86,7 +86,7 @@ struct ZpConfig {
 
 enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
 
-// Per-prime launchers, five translation units per prime (zp_kernels.hip).
+// Per-prime launchers, six translation units per prime (zp_kernels.hip).
 // Return hipSuccess or the launch error (hipErrorInvalidValue for a
 // configuration that is not built).
 typedef hipError_t (*ZpLauncher)(ZpKind kind, const ZpConfig& cfg, const ZpArgs& a,
@@ -121,6 +121,11 @@ struct ZpPrimeEntry {
   // launch shape; group_ext_vec equals group_vec.
   const void* group_ext_kernel;
   int group_ext_vec;
+  // The job-list kernel for batches too small to fill the GPU (the server's):
+  // set for the latency of one tile; same launch shape, tiles of 64 lanes x
+  // group_lat_vec dwords.
+  const void* group_lat_kernel;
+  int group_lat_vec;
 
   // Job-list kernel for jobs with k data strips.
   const void* group_fn(int k) const { return k > p ? group_ext_kernel : group_kernel; }

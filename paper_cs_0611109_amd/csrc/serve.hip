@@ -26,6 +26,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -54,6 +55,10 @@ bool is_odd_prime(int p) {
 }
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Groups of a batch with fewer 256-byte column tiles than this (a few per
+// SIMD of the GPU) run the job-list kernel set for latency.
+constexpr size_t kLatencyTiles = 4096;
 
 struct Pending {
   raid6c_request req;
@@ -103,6 +108,7 @@ struct raid6c_server {
   uint8_t* store = nullptr;
   uint64_t head = 0;             // next free byte (ring)
   std::deque<Resident*> fifo;    // resident stripes, oldest first
+  std::map<uint64_t, Resident*> by_off;  // the same stripes by store offset
   std::unordered_map<uint64_t, Resident*> index;
   std::vector<Slot> slots;
   hipStream_t plain_stream = nullptr;
@@ -151,27 +157,27 @@ Resident* place(raid6c_server* s, const raid6c_request& r, bool* never) {
   for (;;) {
     uint64_t off = s->head;
     if (off + need > s->cfg.store_bytes) off = 0;  // wrap
-    // The span [off, off+need) must be free of resident stripes.
-    bool blocked = false;
+    // The span [off, off+need) must be free of resident stripes: the stripe
+    // with the largest offset below off+need must end at or before off.
     bool overlap = false;
-    for (Resident* o : s->fifo) {
-      if (o->off < off + need && off < o->off + o->bytes) {
-        overlap = true;
-        break;
-      }
+    auto it = s->by_off.lower_bound(off + need);
+    if (it != s->by_off.begin()) {
+      --it;
+      overlap = it->second->off + it->second->bytes > off;
     }
     if (!overlap) {
       Resident* st = new Resident{r.stripe_id, off, need, r.p, r.k, r.row_bytes, 0, false, false};
       s->fifo.push_back(st);
+      s->by_off[off] = st;
       s->index[r.stripe_id] = st;
       s->head = off + need;
       return st;
     }
     // Evict the oldest stripe if it is idle, else wait.
     Resident* oldest = s->fifo.front();
-    if (oldest->refs > 0) blocked = true;
-    if (blocked) return nullptr;
+    if (oldest->refs > 0) return nullptr;
     s->fifo.pop_front();
+    s->by_off.erase(oldest->off);
     s->index.erase(oldest->id);
     delete oldest;
     s->stats.evictions++;
@@ -296,12 +302,32 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     if (sl.reqs[x].stripe->p != sl.reqs[y].stripe->p) return sl.reqs[x].stripe->p > sl.reqs[y].stripe->p;
     return !is_ext(x) && is_ext(y);
   });
+  // A plain-code group too small to fill the GPU takes the job-list kernel
+  // set for latency (four strips per load batch), a larger one the plans'
+  // kernel (set for bandwidth).
   struct Group {
     const ZpPrimeEntry* pe;
     bool ext;
-    uint32_t first, n;
+    size_t begin, end;        // its requests: order[begin, end)
+    const void* fn;
+    uint32_t tile;            // bytes of a column tile
+    uint32_t first, n;        // its items
   };
   std::vector<Group> groups;
+  for (size_t o = 0; o < order.size(); ++o) {
+    const Resident* st = sl.reqs[order[o]].stripe;
+    if (groups.empty() || groups.back().pe->p != st->p || groups.back().ext != is_ext(order[o]))
+      groups.push_back(Group{zp_prime_entry(st->p), is_ext(order[o]), o, o, nullptr, 0, 0, 0});
+    groups.back().end = o + 1;
+  }
+  for (Group& g : groups) {
+    size_t tiles256 = 0;
+    for (size_t o = g.begin; o < g.end; ++o)
+      tiles256 += (sl.reqs[order[o]].stripe->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
+    const bool small = tiles256 < kLatencyTiles;
+    g.fn = g.ext ? g.pe->group_ext_kernel : (small ? g.pe->group_lat_kernel : g.pe->group_kernel);
+    g.tile = 64u * 4u * (uint32_t)(g.ext ? g.pe->group_ext_vec : (small ? g.pe->group_lat_vec : g.pe->group_vec));
+  }
   size_t pitems = 0;  // the persistent kernel's items, first in the table
   if (s->cfg.persistent) {
     // 256-byte tiles of the plain-code requests, in request order.
@@ -310,13 +336,11 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
         for (uint32_t c = 0; c < sl.reqs[i].stripe->row_bytes; c += kBatchTileBytes) h_items[pitems++] = BatchItem{i, c};
   }
   nitems = pitems;
-  for (uint32_t i : order) {
-    const Resident* st = sl.reqs[i].stripe;
-    if (groups.empty() || groups.back().pe->p != st->p || groups.back().ext != is_ext(i))
-      groups.push_back(Group{zp_prime_entry(st->p), is_ext(i), (uint32_t)nitems, 0});
-    const uint32_t tile = 64u * 4u * (uint32_t)groups.back().pe->group_vec;
-    for (uint32_t c = 0; c < st->row_bytes; c += tile) h_items[nitems++] = BatchItem{i, c};
-    groups.back().n = (uint32_t)nitems - groups.back().first;
+  for (Group& g : groups) {
+    g.first = (uint32_t)nitems;
+    for (size_t o = g.begin; o < g.end; ++o)
+      for (uint32_t c = 0; c < sl.reqs[order[o]].stripe->row_bytes; c += g.tile) h_items[nitems++] = BatchItem{order[o], c};
+    g.n = (uint32_t)nitems - g.first;
   }
   // One upload for both tables.
   e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice,
@@ -326,8 +350,8 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     GroupArgs ga{d_jobs, d_items + g.first, g.n};
     void* args[] = {(void*)&ga};
     const int per = g.pe->group_per_wg;
-    e = hipLaunchKernel(g.ext ? g.pe->group_ext_kernel : g.pe->group_kernel, dim3((g.n + per - 1) / per),
-                        dim3(g.pe->group_threads), args, (size_t)g.pe->group_lds, sl.stream);
+    e = hipLaunchKernel(g.fn, dim3((g.n + per - 1) / per), dim3(g.pe->group_threads), args,
+                        (size_t)g.pe->group_lds, sl.stream);
     if (e != hipSuccess) return e;
   }
   if (!s->cfg.persistent || pitems == 0) return hipEventRecord(sl.done, sl.stream);
@@ -370,6 +394,7 @@ void scheduler_loop(raid6c_server* s) {
     // Later requests may pass either.
     Slot& sl = *free_slot;
     sl.reqs.clear();
+    const uint64_t admit0 = s->now_ns();
     const size_t max_batch = s->cfg.plain ? 1 : (size_t)std::max(1, s->cfg.max_batch);
     size_t items = 0;
     std::unordered_set<uint64_t> waiting_writes;  // skipped writes: reads of them wait too
@@ -433,6 +458,8 @@ void scheduler_loop(raid6c_server* s) {
     }
     sl.busy = true;
     s->stats.batches++;
+    const uint64_t launch0 = s->now_ns();
+    s->stats.admit_ns += launch0 - admit0;
     lk.unlock();
     hipError_t e = hipSuccess;
     bool grew = false;
@@ -440,6 +467,7 @@ void scheduler_loop(raid6c_server* s) {
     sl.launch_ns = s->now_ns();
     if (e == hipSuccess) e = launch_slot(s, sl);
     lk.lock();
+    s->stats.launch_ns += s->now_ns() - launch0;
     if (grew) s->stats.table_grows++;
     if (e == hipSuccess) {
       sl.launched = true;
@@ -613,17 +641,24 @@ int raid6c_server_replay(raid6c_server* s, const raid6c_request* reqs, const dou
   }
   // Open loop: request i is submitted at start + arrival_s[i], whatever the
   // state of earlier requests; its latency counts from that scheduled time.
+  // Every request that is due when the loop looks is submitted in one
+  // critical section (all of them at once when the arrival times are 0).
   const uint64_t start = s->now_ns() + 1000000;  // 1 ms to get going
-  for (size_t i = 0; i < n; ++i) {
-    const uint64_t due = start + (uint64_t)(arrival_s[i] * 1e9);
-    while (s->now_ns() < due) {
-      const uint64_t left = due - s->now_ns();
+  auto due_at = [&](size_t i) { return start + (uint64_t)(arrival_s[i] * 1e9); };
+  for (size_t i = 0; i < n;) {
+    const uint64_t due = due_at(i);
+    uint64_t now = s->now_ns();
+    while (now < due) {
+      const uint64_t left = due - now;
       if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
+      now = s->now_ns();
     }
     std::lock_guard<std::mutex> lk(s->mu);
-    s->pending.push_back(Pending{reqs[i], due, i});
-    s->outstanding++;
-    s->stats.submitted++;
+    for (; i < n && due_at(i) <= now; ++i) {
+      s->pending.push_back(Pending{reqs[i], due_at(i), i});
+      s->outstanding++;
+      s->stats.submitted++;
+    }
     s->cv_sched.notify_all();
   }
   std::unique_lock<std::mutex> lk(s->mu);

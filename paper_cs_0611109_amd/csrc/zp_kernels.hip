@@ -1,6 +1,6 @@
 // zp_kernels.hip -- Z_p-RAID encode and recovery kernels for one prime.
 //
-// This file is compiled five times per supported prime, with
+// This file is compiled six times per supported prime, with
 // -DRAID6C_P=<p> and -DRAID6C_VARIANT=
 //   0  the plain code (k <= p), one column slice per thread;
 //   1  the extended Q parity (p < k <= 2p-1, Section 3.3), same mapping;
@@ -8,7 +8,9 @@
 //      share a column tile and split the data strips;
 //   3  the job-list kernel of plans: the tiles of many stripes of this prime,
 //      each with its own geometry, one per wave;
-//   4  the same for stripes with the extended Q parity (p < k <= 2p-1).
+//   4  the same for stripes with the extended Q parity (p < k <= 2p-1);
+//   5  the job-list kernel for small batches of the request server, set for
+//      the latency of one tile rather than for bandwidth.
 // Each object is compiled alone so that the code of one never shapes the
 // compiler's choices for the others; object 0 holds the dispatch entry and
 // calls into the others.
@@ -118,9 +120,9 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 }
 #endif
 
-#if RAID6C_VARIANT == 3 || RAID6C_VARIANT == 4
-// Job-list kernels of plans (variant 3: plain code; variant 4: extended Q
-// parity, k > p).  Work-groups of 4 waves; wave w of
+#if RAID6C_VARIANT >= 3
+// Job-list kernels (variant 3: plans, plain code; variant 4: extended Q
+// parity, k > p; variant 5: the server's small batches).  Work-groups of 4 waves; wave w of
 // work-group b takes item 4b + w: a tile of 64 lanes x GV dwords of one job
 // (any base, strip stride, row size, case), run by tile_recover_one_pass (one
 // streaming pass for every case).  Jobs whose rows are not all on 128-byte lines load
@@ -131,13 +133,21 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 // batch for 37..53 (alone on a 20,000-stripe mix, the p = 37 and 53 grids
 // went from 67% to 72% of peak against vec 1 with four; two strips per batch
 // measured the same); vec 1 with four above, where vec 2 spills.
+// Variant 5 is for batches too small to fill the GPU, where a request's time
+// is the time one wave takes to walk its tile through the k strips: four
+// strips per batch at every prime (a quarter of the load rounds), vec 1
+// above p = 31 (the registers that leaves).
 #if defined(RAID6C_GROUP_VEC)
 constexpr int kGroupVec = RAID6C_GROUP_VEC;
+#elif RAID6C_VARIANT == 5
+constexpr int kGroupVec = kP <= 31 ? 2 : 1;
 #else
 constexpr int kGroupVec = kP <= 53 ? 2 : 1;
 #endif
 #if defined(RAID6C_GROUP_UNROLL)
 constexpr int kGroupUnroll = RAID6C_GROUP_UNROLL;
+#elif RAID6C_VARIANT == 5
+constexpr int kGroupUnroll = 4;
 #else
 constexpr int kGroupUnroll = (kP > 31 && kP <= 53) ? 1 : 4;
 #endif
@@ -168,6 +178,12 @@ __device__ __forceinline__ void group_item(const GroupArgs& a, uint32_t* smem) {
 #if RAID6C_VARIANT == 3
 template <int P>
 __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  group_item<P, false>(a, smem);
+}
+#elif RAID6C_VARIANT == 5
+template <int P>
+__global__ void __launch_bounds__(256) zp_group_lat_kernel(const GroupArgs a) {
   extern __shared__ __align__(16) uint32_t smem[];
   group_item<P, false>(a, smem);
 }
@@ -274,6 +290,7 @@ hipError_t RAID6C_CAT(zp_launch_split_, RAID6C_P)(ZpKind kind, const ZpConfig& c
                                                   hipStream_t stream);
 void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e);
 void RAID6C_CAT(zp_group_ext_shape_, RAID6C_P)(ZpPrimeEntry& e);
+void RAID6C_CAT(zp_group_lat_shape_, RAID6C_P)(ZpPrimeEntry& e);
 
 #if RAID6C_VARIANT == 3
 void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e) {
@@ -282,6 +299,12 @@ void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e) {
   e.group_per_wg = 4;
   e.group_threads = 256;
   e.group_lds = kP * 256 * 4;
+}
+#elif RAID6C_VARIANT == 5
+// Same launch shape as the plan's job-list kernel; its own tile width.
+void RAID6C_CAT(zp_group_lat_shape_, RAID6C_P)(ZpPrimeEntry& e) {
+  e.group_lat_kernel = (const void*)zp_group_lat_kernel<kP>;
+  e.group_lat_vec = kGroupVec;
 }
 #elif RAID6C_VARIANT == 4
 // Same tiles and launch shape as the plain job-list kernel (same constants).
@@ -311,9 +334,10 @@ ZpPrimeEntry make_entry() {
   ZpPrimeEntry e{kP, &launch_plain, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
                  {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)},
                  {0, split_mask(1), split_mask(2), 0, split_mask(4)},
-                 nullptr, 0, 0, 0, 0, nullptr, 0};
+                 nullptr, 0, 0, 0, 0, nullptr, 0, nullptr, 0};
   RAID6C_CAT(zp_group_shape_, RAID6C_P)(e);
   RAID6C_CAT(zp_group_ext_shape_, RAID6C_P)(e);
+  RAID6C_CAT(zp_group_lat_shape_, RAID6C_P)(e);
   return e;
 }
 }  // namespace
