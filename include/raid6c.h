@@ -543,13 +543,17 @@ int raid6c_split_mask(int p, int vec);
 
 /* Record the configuration for (p, op, bucket of row_bytes).  order: 0 =
  * work-groups in dispatch order, 1 = renumbered so that runs of neighbouring
- * column tiles go to one XCD (chiplet with its own L2) together.  A launch
- * whose rows do not all start on 128-byte lines (row_bytes, strip addresses
- * and strides not multiples of 128) always takes order 1 and loads through
- * the caches; otherwise loads are non-temporal.
+ * column tiles go to one XCD (chiplet with its own L2) together, 2 = the
+ * stripes of consecutive work-groups spread over the launch (stripe s is
+ * handled in place m*s mod n for a fixed m coprime with the n stripes of the
+ * launch), so that the work in flight does not sit at the same offsets of
+ * neighbouring stripes.  A launch whose rows do not all start on 128-byte
+ * lines (row_bytes, strip addresses and strides not multiples of 128) takes
+ * order 1 in place of 0 and loads through the caches; otherwise loads are
+ * non-temporal.
  * Errors: RAID6C_E_ARG for an unbuilt p, op not 0..3, (vec, unroll) not built
  * for p, threads not 64/128/256, split not 1 or a built factor with
- * threads = 64*split, or order not 0/1. */
+ * threads = 64*split, or order not 0..2. */
 int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int threads, int split, int order);
 
 /* The configuration a call with these arguments would use now.
@@ -563,10 +567,12 @@ void raid6c_tune_clear(void);
 /* Autotuner for the strided entry points: run every built (vec, unroll,
  * threads, split) configuration on the caller's stripes -- op 0: raid6c_encode_n,
  * op 1: raid6c_recover_n with `erasures` (device, as there) -- once to warm
- * up and `reps` times timed with HIP events on `stream`, then record the
- * fastest for (p, op, row-size bucket) -- op + 2 when k > p -- and return its
- * mean time per launch
- * in *best_ms (may be NULL).  Every run rewrites the same output bytes.
+ * up and `reps` times, each launch timed with HIP events on `stream`, in
+ * every work-group order (0, 1 and 2, the latter two for the configurations
+ * within 5% of the best), then record the one with the smallest median
+ * launch time for (p, op, row-size bucket) -- op + 2 when k > p -- and
+ * return that median in *best_ms (may be NULL).  Every run rewrites the same
+ * output bytes.
  * Synchronises.  Errors: as raid6c_encode_n / raid6c_recover_n, plus
  * RAID6C_E_ARG for op not 0/1 or reps outside 1..1000, RAID6C_E_HIP. */
 int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base,

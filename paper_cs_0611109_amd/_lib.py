@@ -384,9 +384,10 @@ RAID6C_NOALLOC_MAX_JOBS = 4096
 RAID6C_NOALLOC_MAX_ITEMS = 262144
 
 
-def raid6c_autotune_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, op, erasures=None, reps=5,
+def raid6c_autotune_n(p, k, row_bytes, base, strip_stride, stripe_stride, nstripes, op, erasures=None, reps=20,
                       stream=None) -> float:
-    """Pick and record the fastest launch configuration; returns its ms per launch."""
+    """Pick and record the configuration with the smallest median launch time;
+    returns that median in ms."""
     ms = ctypes.c_float()
     _check(load().raid6c_autotune_n(p, k, row_bytes, _ptr(base), strip_stride, stripe_stride, nstripes, op,
                                     _ptr(erasures), reps, _stream(stream), ctypes.byref(ms)))

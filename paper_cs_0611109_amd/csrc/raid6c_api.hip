@@ -7,7 +7,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/raid6c.h"
 #include "raid6c_internal.h"
@@ -146,6 +148,25 @@ static int check_strip_ptrs(int n, const void* const* ptrs, size_t strip_bytes) 
   return RAID6C_OK;
 }
 
+// Multiplier of work-group order 2: near n / golden ratio, coprime with n,
+// so that s -> m*s mod n permutes the n stripes of a launch and places
+// consecutive work-groups far apart.
+static uint32_t scatter_multiplier(size_t n) {
+  if (n < 3) return 1u;
+  uint64_t m = (uint64_t)((double)n * 0.6180339887498949);
+  if (m < 1) m = 1;
+  auto gcd = [](uint64_t a, uint64_t b) {
+    while (b != 0) {
+      const uint64_t t = a % b;
+      a = b;
+      b = t;
+    }
+    return a;
+  };
+  while (gcd(m, n) != 1) ++m;
+  return (uint32_t)m;
+}
+
 // Launch a Z_p kernel over `nstripes` stripes, splitting the grid when needed.
 static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream) {
   if (nstripes == 0) return RAID6C_OK;
@@ -163,7 +184,7 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
                        a.src_stripe_stride;
   for (int j = 0; j < a.k + 2; ++j) addr_bits |= (uintptr_t)a.strip[j];
   a.shared_lines = (addr_bits & 127u) != 0;
-  a.xcd_order = a.shared_lines || cfg.order != 0;
+  a.xcd_order = cfg.order == 1 || (a.shared_lines && cfg.order == 0);
   // Keep grid * threads below 2^31.
   const uint64_t max_blocks = (((uint64_t)1 << 31) / cfg.threads);
   const uint64_t chunk = max_blocks / a.tiles;
@@ -178,6 +199,7 @@ static int launch_zp(int p, ZpKind kind, ZpArgs a, size_t nstripes, void* stream
       if (a.src_base != nullptr) b.src_base = a.src_base + done * a.src_stripe_stride;
     }
     b.nstripes = (uint32_t)n;
+    b.stripe_mult = cfg.order == 2 ? scatter_multiplier(n) : 0u;
     // Split-K configurations (plain or extended) go through the plain entry,
     // which hands them to the split object.
     const ZpLauncher fn = (a.k > p && !split) ? e->launch_ext : e->launch;
@@ -553,7 +575,7 @@ int raid6c_tune_set(int p, int op, size_t row_bytes, int vec, int unroll, int th
   if (!e->has(ZpConfig{vec, unroll, threads, split}))
     return fail(RAID6C_E_ARG, "split = %d is not built for p = %d, vec = %d with threads = %d", split, p, vec,
                 threads);
-  if (order != 0 && order != 1) return fail(RAID6C_E_ARG, "order = %d must be 0 or 1", order);
+  if (order < 0 || order > 2) return fail(RAID6C_E_ARG, "order = %d must be 0, 1 or 2", order);
   if (row_bytes == 0) return fail(RAID6C_E_ARG, "row_bytes must be positive");
   set_tuned(p, op, row_bucket(row_bytes), ZpConfig{vec, unroll, threads, split, order});
   return RAID6C_OK;
@@ -601,12 +623,14 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
     return RAID6C_OK;
   }
   const hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return fail(RAID6C_E_HIP, "hipEventCreate failed");
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return fail(RAID6C_E_HIP, "hipEventCreate failed");
-  }
+  // One event before each timed launch and one after the last.
+  std::vector<hipEvent_t> ev((size_t)reps + 1, nullptr);
+  for (hipEvent_t& x : ev)
+    if (hipEventCreate(&x) != hipSuccess) {
+      for (hipEvent_t& y : ev)
+        if (y != nullptr) (void)hipEventDestroy(y);
+      return fail(RAID6C_E_HIP, "hipEventCreate failed");
+    }
   const ZpKind kind = op == 0 ? KIND_ENCODE : KIND_RECOVER;
   const int slot = tune_slot(kind, k > p);
   const int bucket = row_bucket(row_bytes);
@@ -626,18 +650,23 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
       for (int sp = 2; sp <= 4; sp *= 2)
         if (e->split_mask[vec] & sp) cands[ncand++] = ZpConfig{vec, unroll, 64 * sp, sp};
     }
-  // Mean time per launch of one configuration (after one warm-up launch).
+  // Median time per launch of one configuration over `reps` launches timed
+  // one by one (after one warm-up launch).
+  std::vector<float> t((size_t)reps);
   auto time_cfg = [&](const ZpConfig& cfg, float* ms) {
     set_tuned(p, slot, bucket, cfg);
     int r2 = launch_zp(p, kind, a, nstripes, stream);
     if (r2 != RAID6C_OK) return r2;
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps && r2 == RAID6C_OK; ++r) r2 = launch_zp(p, kind, a, nstripes, stream);
-    (void)hipEventRecord(e1, s);
+    (void)hipEventRecord(ev[0], s);
+    for (int r = 0; r < reps && r2 == RAID6C_OK; ++r) {
+      r2 = launch_zp(p, kind, a, nstripes, stream);
+      (void)hipEventRecord(ev[(size_t)r + 1], s);
+    }
     if (r2 != RAID6C_OK) return r2;
-    if (hipEventSynchronize(e1) != hipSuccess) return fail(RAID6C_E_HIP, "hipEventSynchronize failed");
-    (void)hipEventElapsedTime(ms, e0, e1);
-    *ms /= (float)reps;
+    if (hipEventSynchronize(ev[(size_t)reps]) != hipSuccess) return fail(RAID6C_E_HIP, "hipEventSynchronize failed");
+    for (int r = 0; r < reps; ++r) (void)hipEventElapsedTime(&t[(size_t)r], ev[(size_t)r], ev[(size_t)r + 1]);
+    std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+    *ms = t[(size_t)reps / 2];
     return RAID6C_OK;
   };
   float times[9 * 5];
@@ -648,21 +677,23 @@ int raid6c_autotune_n(int p, int k, size_t row_bytes, void* base, size_t strip_s
       best = cands[ci];
     }
   }
-  // The XCD-chunked work-group order for the configurations within 5% of
-  // the best.
+  // The other work-group orders (XCD-chunked, stripes spread) for the
+  // configurations within 5% of the best.
+  const float cut = 1.05f * best_t;
   for (int ci = 0; ci < ncand && rc == RAID6C_OK; ++ci) {
-    if (times[ci] > 1.05f * best_t) continue;
-    ZpConfig cfg = cands[ci];
-    cfg.order = 1;
-    float ms = 0.f;
-    rc = time_cfg(cfg, &ms);
-    if (rc == RAID6C_OK && ms < best_t) {
-      best_t = ms;
-      best = cfg;
+    if (times[ci] > cut) continue;
+    for (int order = 1; order <= 2 && rc == RAID6C_OK; ++order) {
+      ZpConfig cfg = cands[ci];
+      cfg.order = order;
+      float ms = 0.f;
+      rc = time_cfg(cfg, &ms);
+      if (rc == RAID6C_OK && ms < best_t) {
+        best_t = ms;
+        best = cfg;
+      }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (hipEvent_t& x : ev) (void)hipEventDestroy(x);
   if (rc != RAID6C_OK) return rc;
   set_tuned(p, slot, bucket, best);
   if (best_ms) *best_ms = best_t;

@@ -73,6 +73,7 @@ struct ZpArgs {
   int32_t kind;                // ZpKind of the launch (set by the launcher)
   int32_t shared_lines;        // some row does not start on a 128-byte line (set by the launcher)
   int32_t xcd_order;           // XCD-chunked work-group order (set by the launcher)
+  uint32_t stripe_mult;        // 0, or work-group order 2: stripe s -> s*stripe_mult mod nstripes
 };
 
 // Launch configuration of a Z_p kernel.
@@ -81,7 +82,8 @@ struct ZpConfig {
   int unroll;     // data strips whose loads are issued together: 1, 2 or 4
   int threads;    // work-group size: 64, 128 or 256
   int split = 1;  // waves sharing one column tile (1, 2, 4); threads = 64*split when > 1
-  int order = 0;  // 1: XCD-chunked work-group order (always taken when rows are off 128-byte lines)
+  int order = 0;  // 1: XCD-chunked work-group order (always taken when rows are off 128-byte lines);
+                  // 2: stripes spread over the launch (a fixed permutation of the stripe index)
 };
 
 enum ZpKind : int { KIND_ENCODE = 0, KIND_RECOVER = 1 };
@@ -135,7 +137,7 @@ struct ZpPrimeEntry {
            (unroll == 1 || unroll == 2 || unroll == 4) && (unroll_mask[vec] & unroll);
   }
   bool has(const ZpConfig& c) const {
-    if (!has(c.vec, c.unroll) || (c.order != 0 && c.order != 1)) return false;
+    if (!has(c.vec, c.unroll) || c.order < 0 || c.order > 2) return false;
     if (c.split == 1) return c.threads == 64 || c.threads == 128 || c.threads == 256;
     return (c.split == 2 || c.split == 4) && (split_mask[c.vec] & c.split) && c.threads == 64 * c.split;
   }

@@ -48,6 +48,14 @@ static_assert(kP >= 3 && kP <= kMaxPrime && (kP % 2) == 1, "unsupported prime");
 // are a multiple of its tile it beat vec 1 by 2-6 points of peak.
 constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (1 | 2);
 
+// Work-group order 2: the stripes of consecutive work-groups are spread over
+// the launch, stripe s -> s * m mod n with gcd(m, n) = 1 (a permutation), so
+// that the work-groups in flight at one time do not all touch the same
+// offsets of neighbouring stripes.
+__device__ __forceinline__ uint32_t scatter_stripe(uint32_t s, const ZpArgs& a) {
+  return a.stripe_mult == 0u ? s : (uint32_t)(((uint64_t)s * a.stripe_mult) % a.nstripes);
+}
+
 // EXT: k > p data strips with the extended Q parity of Section 3.3.  LP: cache
 // policy of the loads (non-temporal, or the ordinary one when rows do not all
 // start on 128-byte lines, whose edge lines two tiles read).  The work-group
@@ -56,8 +64,8 @@ constexpr int kVecMask = (kP <= 13) ? (1 | 2 | 4) : (1 | 2);
 template <int P, int V, int U, bool EXT, int LP>
 __global__ void __launch_bounds__(256) zp_encode_kernel(const ZpArgs a) {
   const uint32_t bid = a.xcd_order ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
-  const uint32_t stripe = bid / a.tiles;
-  const uint32_t tile = bid - stripe * a.tiles;
+  const uint32_t tile = bid % a.tiles;
+  const uint32_t stripe = scatter_stripe(bid / a.tiles, a);
   const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
   if (col >= a.row_bytes) return;
   const ColsTableP<LP> c{&a, (uint64_t)stripe * a.stripe_stride, (uint64_t)stripe * a.src_stripe_stride, col,
@@ -69,8 +77,8 @@ template <int P, int V, int U, bool EXT, int LP>
 __global__ void __launch_bounds__(256) zp_recover_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t bid = a.xcd_order ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
-  const uint32_t stripe = bid / a.tiles;
-  const uint32_t tile = bid - stripe * a.tiles;
+  const uint32_t tile = bid % a.tiles;
+  const uint32_t stripe = scatter_stripe(bid / a.tiles, a);
   int e0 = a.e0, e1 = a.e1;
   if (a.erasures != nullptr) {
     // One stripe per work-group: the entry is uniform.  Saying so keeps the
@@ -97,8 +105,8 @@ template <int P, int V, int U, int S, bool EXT, int LP>
 __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
   extern __shared__ __align__(16) uint32_t part[];
   const uint32_t bid = a.xcd_order ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
-  const uint32_t stripe = bid / a.tiles;
-  const uint32_t tile = bid - stripe * a.tiles;
+  const uint32_t tile = bid % a.tiles;
+  const uint32_t stripe = scatter_stripe(bid / a.tiles, a);
   Case cs{OP_PQ, -1, -1};            // an encode writes P and Q
   if (a.kind == KIND_RECOVER) {
     // Per-stripe entries, or the uniform pair of a single-stripe call.

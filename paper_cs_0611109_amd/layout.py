@@ -53,7 +53,7 @@ class StripeBatch:
         return _lib.raid6c_recover_n(self.p, self.k, self.row_bytes, base, self.strip_stride,
                                      self.stripe_stride, n, eptr, bad_count, stream)
 
-    def autotune(self, op: int, erasures=None, reps: int = 5, stream=None) -> float:
+    def autotune(self, op: int, erasures=None, reps: int = 20, stream=None) -> float:
         """Record the fastest launch configuration for this geometry (op 0 encode, 1 recovery)."""
         return _lib.raid6c_autotune_n(self.p, self.k, self.row_bytes, self.tensor.data_ptr(), self.strip_stride,
                                       self.stripe_stride, self.nstripes, op, erasures, reps, stream)

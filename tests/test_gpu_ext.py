@@ -126,8 +126,9 @@ def test_extended_every_launch_configuration(p):
             # split-K entries run the split-K extended kernels
             cfgs = [(t, 1) for t in (64, 128, 256)] + [(64 * sp, sp) for sp in (2, 4) if r.raid6c_split_mask(p, v) & sp]
             for t, sp in cfgs:
-                log(f"extended config p={p} k={k} vec={v} unroll={u} threads={t} split={sp}")
-                _set_ext(p, w, v, u, t, sp)
+                order = (v + u + t // 64 + sp) % 3
+                log(f"extended config p={p} k={k} vec={v} unroll={u} threads={t} split={sp} order={order}")
+                _set_ext(p, w, v, u, t, sp, order)
                 assert np.array_equal(_encode(want[:2], p, k, w), want[:2]), (v, u, t, sp)
                 assert np.array_equal(_recover(want, p, k, w, er), want), (v, u, t, sp)
     r.raid6c_tune_clear()

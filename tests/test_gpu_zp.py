@@ -103,8 +103,9 @@ def test_every_launch_config(p):
     for k in sorted({min(p, 6), p}):
         for ci, (v, u, t, sp) in enumerate(_configs(p)):
             # 128: rows on cache lines (non-temporal loads, work-group order
-            # as configured: alternating); the others not (chunked order).
-            order = ci % 2
+            # as configured: each of the three in turn); the others not
+            # (chunked order, or spread stripes when order 2 is configured).
+            order = ci % 3
             for w in (16, 128, 64 * 4 * v + 16):
                 log(f"config p={p} k={k} vec={v} unroll={u} threads={t} split={sp} order={order} W={w}")
                 r.raid6c_tune_set(p, 0, w, v, u, t, sp, order)
@@ -260,7 +261,7 @@ def test_every_config_every_two_erasure_kind_many_stripes(p, w):
     n = 192
     want = zp.encode_stripe(datagen.fill_stripes(p, 0, n, k, p, w), p)
     for ci, (v, u, t, sp) in enumerate(_configs(p)):
-        order = ci % 2                  # both work-group orders; grids of 10^3 work-groups
+        order = ci % 3                  # every work-group order; grids of 10^3 work-groups
         r.raid6c_tune_set(p, 0, w, v, u, t, sp, order)
         r.raid6c_tune_set(p, 1, w, v, u, t, sp, order)
         log(f"many stripes p={p} W={w} vec={v} unroll={u} threads={t} split={sp} order={order}")
@@ -295,7 +296,7 @@ def test_rows_off_lines_many_work_groups(p, k, w, n):
 
 def _built(p, cfg):
     v, u, t, sp, order = cfg
-    return (r.raid6c_unroll_mask(p, v) & u and order in (0, 1) and
+    return (r.raid6c_unroll_mask(p, v) & u and order in (0, 1, 2) and
             (sp == 1 and t in (64, 128, 256) or r.raid6c_split_mask(p, v) & sp and t == 64 * sp))
 
 
