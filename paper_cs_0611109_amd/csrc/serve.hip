@@ -16,6 +16,12 @@
 // slots' events, stamps completion times and releases stripes.  With
 // `plain` set, every request is instead one plain launch (raid6c_write /
 // raid6c_read_degraded) on a single stream: the per-request path.
+//
+// A degraded read of a stripe whose write is admitted in the same batch runs
+// in the batch's second launch phase, after the first phase that holds the
+// write; a read of a stripe whose write is in another slot's batch in flight
+// is parked on the host until that write completes (waiting on the device
+// would hold the read's whole batch behind the other one).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -66,6 +72,8 @@ struct Pending {
   size_t index;    // position in a replay, else SIZE_MAX
 };
 
+struct Slot;
+
 struct Resident {
   uint64_t id;
   uint64_t off;    // byte offset in the store
@@ -74,8 +82,9 @@ struct Resident {
   uint32_t row_bytes;
   int refs;        // admitted requests not yet complete
   bool ready;      // its write has completed
-  bool evicted;
-  std::vector<Pending> waiters;  // reads that arrived before the write completed
+  bool failed;     // its write could not be launched: reads of it are invalid
+  Slot* writer;    // the slot whose batch writes it, while that is in flight
+  std::vector<Pending> waiters;  // reads parked until that write completes
 };
 
 struct InFlight {
@@ -83,6 +92,7 @@ struct InFlight {
   uint64_t arrival_ns;
   size_t index;
   Resident* stripe;
+  int phase;       // 1: a read of a stripe written in the same batch (runs after phase 0)
 };
 
 struct Slot {
@@ -118,9 +128,9 @@ struct raid6c_server {
   std::condition_variable cv_done;   // completions
   std::deque<Pending> pending;
   std::deque<raid6c_completion> done;
+  size_t parked = 0;                 // reads waiting in a stripe's waiters
   raid6c_completion* replay_out = nullptr;
   size_t outstanding = 0;            // submitted, not complete
-  size_t parked = 0;                 // reads waiting in a stripe's waiters
   bool stopping = false;
   raid6c_server_stats stats{};
   Clock::time_point t0 = Clock::now();
@@ -166,7 +176,7 @@ Resident* place(raid6c_server* s, const raid6c_request& r, bool* never) {
       overlap = it->second->off + it->second->bytes > off;
     }
     if (!overlap) {
-      Resident* st = new Resident{r.stripe_id, off, need, r.p, r.k, r.row_bytes, 0, false, false};
+      Resident* st = new Resident{r.stripe_id, off, need, r.p, r.k, r.row_bytes, 0, false, false, nullptr};
       s->fifo.push_back(st);
       s->by_off[off] = st;
       s->index[r.stripe_id] = st;
@@ -257,6 +267,15 @@ void fill_job(const raid6c_server* s, const InFlight& f, BatchJob& j) {
   }
 }
 
+// The reads parked on a stripe go back to the head of the queue, oldest
+// first (its write has completed or failed).  Called with the lock held.
+void release_waiters(raid6c_server* s, Resident* st) {
+  std::vector<Pending>& w = st->waiters;
+  for (auto pw = w.rbegin(); pw != w.rend(); ++pw) s->pending.push_front(*pw);
+  s->parked -= w.size();
+  w.clear();
+}
+
 // Launch one slot's requests.  Called without the lock.
 hipError_t launch_slot(raid6c_server* s, Slot& sl) {
   if (s->cfg.plain) {
@@ -288,23 +307,18 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
   const BatchJob* d_jobs = (const BatchJob*)(d_tab + jobs_off);
   const BatchItem* d_items = (const BatchItem*)d_tab;
   hipError_t e;
-  // Grids of the job-list kernels (as in a plan's grouped schedule): the
-  // requests of one prime and one code (plain, or extended Q parity: k > p)
-  // form a grid, largest prime first; items are that prime's tiles (at least
-  // kBatchTileBytes, so the table holds them).  With `persistent` set, only
-  // the extended-parity requests go this way (the persistent kernel runs the
-  // plain code), and their items follow the persistent kernel's.
+  // Per launch phase (0: everything but phase-1 reads; 1: reads of stripes
+  // written in phase 0), grids of the job-list kernels (as in a plan's
+  // grouped schedule): the requests of one prime and one code (plain, or
+  // extended Q parity: k > p) form a grid, largest prime first; items are
+  // that prime's tiles (at least kBatchTileBytes, so the table holds them).
+  // With `persistent` set, the plain-code requests of a phase run as one
+  // persistent kernel over 256-byte tiles instead (the persistent kernel runs
+  // the plain code only); the extended-parity ones still go by grid.  A
+  // plain-code group too small to fill the GPU takes the job-list kernel set
+  // for latency (four strips per load batch), a larger one the plans' kernel
+  // (set for bandwidth).
   auto is_ext = [&](uint32_t i) { return sl.reqs[i].stripe->k > sl.reqs[i].stripe->p; };
-  std::vector<uint32_t> order;
-  for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
-    if (!s->cfg.persistent || is_ext(i)) order.push_back(i);
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-    if (sl.reqs[x].stripe->p != sl.reqs[y].stripe->p) return sl.reqs[x].stripe->p > sl.reqs[y].stripe->p;
-    return !is_ext(x) && is_ext(y);
-  });
-  // A plain-code group too small to fill the GPU takes the job-list kernel
-  // set for latency (four strips per load batch), a larger one the plans'
-  // kernel (set for bandwidth).
   struct Group {
     const ZpPrimeEntry* pe;
     bool ext;
@@ -313,63 +327,82 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     uint32_t tile;            // bytes of a column tile
     uint32_t first, n;        // its items
   };
-  std::vector<Group> groups;
-  for (size_t o = 0; o < order.size(); ++o) {
-    const Resident* st = sl.reqs[order[o]].stripe;
-    if (groups.empty() || groups.back().pe->p != st->p || groups.back().ext != is_ext(order[o]))
-      groups.push_back(Group{zp_prime_entry(st->p), is_ext(order[o]), o, o, nullptr, 0, 0, 0});
-    groups.back().end = o + 1;
-  }
-  for (Group& g : groups) {
-    size_t tiles256 = 0;
-    for (size_t o = g.begin; o < g.end; ++o)
-      tiles256 += (sl.reqs[order[o]].stripe->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
-    const bool small = tiles256 < kLatencyTiles;
-    g.fn = g.ext ? g.pe->group_ext_kernel : (small ? g.pe->group_lat_kernel : g.pe->group_kernel);
-    g.tile = 64u * 4u * (uint32_t)(g.ext ? g.pe->group_ext_vec : (small ? g.pe->group_lat_vec : g.pe->group_vec));
-  }
-  size_t pitems = 0;  // the persistent kernel's items, first in the table
-  if (s->cfg.persistent) {
-    // 256-byte tiles of the plain-code requests, in request order.
+  struct Phase {
+    std::vector<uint32_t> order;  // requests that go by grid
+    std::vector<Group> groups;
+    uint32_t pfirst = 0, pn = 0;  // persistent kernel's items
+  };
+  Phase ph[2];
+  nitems = 0;
+  for (int f = 0; f < 2; ++f) {
+    Phase& P = ph[f];
     for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
-      if (!is_ext(i))
-        for (uint32_t c = 0; c < sl.reqs[i].stripe->row_bytes; c += kBatchTileBytes) h_items[pitems++] = BatchItem{i, c};
-  }
-  nitems = pitems;
-  for (Group& g : groups) {
-    g.first = (uint32_t)nitems;
-    for (size_t o = g.begin; o < g.end; ++o)
-      for (uint32_t c = 0; c < sl.reqs[order[o]].stripe->row_bytes; c += g.tile) h_items[nitems++] = BatchItem{order[o], c};
-    g.n = (uint32_t)nitems - g.first;
+      if (sl.reqs[i].phase == f && (!s->cfg.persistent || is_ext(i))) P.order.push_back(i);
+    std::stable_sort(P.order.begin(), P.order.end(), [&](uint32_t x, uint32_t y) {
+      if (sl.reqs[x].stripe->p != sl.reqs[y].stripe->p) return sl.reqs[x].stripe->p > sl.reqs[y].stripe->p;
+      return !is_ext(x) && is_ext(y);
+    });
+    for (size_t o = 0; o < P.order.size(); ++o) {
+      const Resident* st = sl.reqs[P.order[o]].stripe;
+      if (P.groups.empty() || P.groups.back().pe->p != st->p || P.groups.back().ext != is_ext(P.order[o]))
+        P.groups.push_back(Group{zp_prime_entry(st->p), is_ext(P.order[o]), o, o, nullptr, 0, 0, 0});
+      P.groups.back().end = o + 1;
+    }
+    for (Group& g : P.groups) {
+      size_t tiles256 = 0;
+      for (size_t o = g.begin; o < g.end; ++o)
+        tiles256 += (sl.reqs[P.order[o]].stripe->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
+      const bool small = tiles256 < kLatencyTiles;
+      g.fn = g.ext ? g.pe->group_ext_kernel : (small ? g.pe->group_lat_kernel : g.pe->group_kernel);
+      g.tile = 64u * 4u * (uint32_t)(g.ext ? g.pe->group_ext_vec : (small ? g.pe->group_lat_vec : g.pe->group_vec));
+    }
+    if (s->cfg.persistent) {
+      // 256-byte tiles of the phase's plain-code requests, in request order.
+      P.pfirst = (uint32_t)nitems;
+      for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
+        if (sl.reqs[i].phase == f && !is_ext(i))
+          for (uint32_t c = 0; c < sl.reqs[i].stripe->row_bytes; c += kBatchTileBytes)
+            h_items[nitems++] = BatchItem{i, c};
+      P.pn = (uint32_t)nitems - P.pfirst;
+    }
+    for (Group& g : P.groups) {
+      g.first = (uint32_t)nitems;
+      for (size_t o = g.begin; o < g.end; ++o)
+        for (uint32_t c = 0; c < sl.reqs[P.order[o]].stripe->row_bytes; c += g.tile)
+          h_items[nitems++] = BatchItem{P.order[o], c};
+      g.n = (uint32_t)nitems - g.first;
+    }
   }
   // One upload for both tables.
   e = hipMemcpyAsync(d_tab, sl.h_buf, jobs_off + sl.reqs.size() * sizeof(BatchJob), hipMemcpyHostToDevice,
                      sl.stream);
   if (e != hipSuccess) return e;
-  for (const Group& g : groups) {
-    GroupArgs ga{d_jobs, d_items + g.first, g.n};
-    void* args[] = {(void*)&ga};
-    const int per = g.pe->group_per_wg;
-    e = hipLaunchKernel(g.fn, dim3((g.n + per - 1) / per), dim3(g.pe->group_threads), args,
-                        (size_t)g.pe->group_lds, sl.stream);
-    if (e != hipSuccess) return e;
-  }
-  if (!s->cfg.persistent || pitems == 0) return hipEventRecord(sl.done, sl.stream);
-  // One persistent kernel over the plain-code requests' 256-byte tiles.
-  nitems = pitems;
   int max_p = 3;
   for (const InFlight& f : sl.reqs) max_p = std::max(max_p, f.stripe->p);
-  const int waves = s->cfg.waves_per_cu > 0 ? s->cfg.waves_per_cu : 8;
-  int grid = s->cus * waves;
-  // Small batches: one item per pop, so that every item has a wave of its
-  // own (their tiles are latency-bound walks over the strips).
-  const uint32_t chunk = nitems <= (size_t)grid * 2 ? 1u : 4u;
-  BatchArgs a{d_jobs, d_items, (uint32_t)nitems, chunk, d_counter, sl.counter};
-  const int need = (int)((nitems + a.chunk - 1) / a.chunk);
-  if (need < grid) grid = std::max(1, need);
-  e = batch_launch(a, grid, max_p, sl.stream);
-  if (e != hipSuccess) return e;
-  sl.counter = batch_counter_after(sl.counter, a.nitems, a.chunk, (uint32_t)grid);
+  for (int f = 0; f < 2; ++f) {
+    const Phase& P = ph[f];
+    for (const Group& g : P.groups) {
+      GroupArgs ga{d_jobs, d_items + g.first, g.n};
+      void* args[] = {(void*)&ga};
+      const int per = g.pe->group_per_wg;
+      e = hipLaunchKernel(g.fn, dim3((g.n + per - 1) / per), dim3(g.pe->group_threads), args,
+                          (size_t)g.pe->group_lds, sl.stream);
+      if (e != hipSuccess) return e;
+    }
+    if (P.pn == 0) continue;
+    // One persistent kernel over the phase's plain-code requests.
+    const int waves = s->cfg.waves_per_cu > 0 ? s->cfg.waves_per_cu : 8;
+    int grid = s->cus * waves;
+    // Small batches: one item per pop, so that every item has a wave of its
+    // own (their tiles are latency-bound walks over the strips).
+    const uint32_t chunk = P.pn <= (uint32_t)grid * 2 ? 1u : 4u;
+    BatchArgs a{d_jobs, d_items + P.pfirst, P.pn, chunk, d_counter, sl.counter};
+    const int need = (int)((P.pn + a.chunk - 1) / a.chunk);
+    if (need < grid) grid = std::max(1, need);
+    e = batch_launch(a, grid, max_p, sl.stream);
+    if (e != hipSuccess) return e;
+    sl.counter = batch_counter_after(sl.counter, a.nitems, a.chunk, (uint32_t)grid);
+  }
   return hipEventRecord(sl.done, sl.stream);
 }
 
@@ -388,10 +421,11 @@ void scheduler_loop(raid6c_server* s) {
       s->cv_sched.wait(lk);
       continue;
     }
-    // Admit requests in arrival order.  A read of a stripe whose write is in
-    // flight is parked on the stripe until that write completes; a write
-    // that must wait for room, and reads of it, are skipped in this pass.
-    // Later requests may pass either.
+    // Admit requests in arrival order.  A read of a stripe written in this
+    // batch runs in its second launch phase; a read of a stripe whose write
+    // is in another batch in flight is parked on the stripe until that write
+    // completes; a write that must wait for room, and reads of it, are
+    // skipped in this pass.  Later requests may pass them.
     Slot& sl = *free_slot;
     sl.reqs.clear();
     const uint64_t admit0 = s->now_ns();
@@ -422,15 +456,15 @@ void scheduler_loop(raid6c_server* s) {
           status = RAID6C_ST_NOT_RESIDENT;
         } else {
           st = f->second;
-          if (!st->ready) {
+          if (st->failed || classify(st->k, r.e0, r.e1).op == OP_BAD || r.dst == nullptr ||
+              ((uintptr_t)r.dst & 15u) != 0) {
+            status = RAID6C_ST_INVALID;
+            st = nullptr;
+          } else if (!st->ready && st->writer != &sl) {
             st->waiters.push_back(*it);
             s->parked++;
             it = s->pending.erase(it);
             continue;
-          } else if (classify(st->k, r.e0, r.e1).op == OP_BAD || r.dst == nullptr ||
-                     ((uintptr_t)r.dst & 15u) != 0) {
-            status = RAID6C_ST_INVALID;
-            st = nullptr;
           }
         }
       }
@@ -447,7 +481,10 @@ void scheduler_loop(raid6c_server* s) {
         continue;
       }
       st->refs++;
-      sl.reqs.push_back(InFlight{r, it->arrival_ns, it->index, st});
+      int phase = 0;
+      if (r.kind == RAID6C_REQ_WRITE) st->writer = &sl;
+      else if (!st->ready) phase = 1;   // written in this batch
+      sl.reqs.push_back(InFlight{r, it->arrival_ns, it->index, st, phase});
       items += (st->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
       it = s->pending.erase(it);
     }
@@ -479,6 +516,11 @@ void scheduler_loop(raid6c_server* s) {
       const uint64_t t = s->now_ns();
       for (const InFlight& f : sl.reqs) {
         f.stripe->refs--;
+        if (f.req.kind == RAID6C_REQ_WRITE) {
+          f.stripe->failed = true;
+          f.stripe->writer = nullptr;
+          release_waiters(s, f.stripe);
+        }
         complete_one(s, f.req, f.arrival_ns, f.index, RAID6C_ST_INVALID, t, t, 0);
       }
       sl.reqs.clear();
@@ -516,12 +558,10 @@ void completer_loop(raid6c_server* s) {
       const int n = (int)sl.reqs.size();
       for (const InFlight& f : sl.reqs) {
         if (f.req.kind == RAID6C_REQ_WRITE) {
-          f.stripe->ready = true;
-          // Its parked reads go back to the head of the queue, oldest first.
-          std::vector<Pending>& w = f.stripe->waiters;
-          for (auto pw = w.rbegin(); pw != w.rend(); ++pw) s->pending.push_front(*pw);
-          s->parked -= w.size();
-          w.clear();
+          f.stripe->ready = q == hipSuccess;
+          f.stripe->failed = q != hipSuccess;
+          f.stripe->writer = nullptr;
+          release_waiters(s, f.stripe);
         }
         f.stripe->refs--;
         const uint64_t user = (uint64_t)f.stripe->k * (f.stripe->p - 1) * f.stripe->row_bytes;
