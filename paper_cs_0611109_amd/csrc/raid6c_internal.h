@@ -124,10 +124,13 @@ struct ZpPrimeEntry {
   const void* group_ext_kernel;
   int group_ext_vec;
   // The job-list kernel for batches too small to fill the GPU (the server's):
-  // set for the latency of one tile; same launch shape, tiles of 64 lanes x
-  // group_lat_vec dwords.
+  // set for the latency of one tile.  Tiles of 64 lanes x group_lat_vec
+  // dwords, one per work-group of group_lat_threads threads (its waves split
+  // the strips), group_lat_lds bytes of dynamic LDS.
   const void* group_lat_kernel;
   int group_lat_vec;
+  int group_lat_threads;
+  int group_lat_lds;
 
   // Job-list kernel for jobs with k data strips.
   const void* group_fn(int k) const { return k > p ? group_ext_kernel : group_kernel; }

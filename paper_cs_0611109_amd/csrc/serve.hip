@@ -66,6 +66,9 @@ uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // SIMD of the GPU) run the job-list kernel set for latency.
 constexpr size_t kLatencyTiles = 4096;
 
+// Largest batch formed while no other batch is in flight.
+constexpr size_t kIdleBatch = 128;
+
 struct Pending {
   raid6c_request req;
   uint64_t arrival_ns;
@@ -316,8 +319,8 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
   // persistent kernel over 256-byte tiles instead (the persistent kernel runs
   // the plain code only); the extended-parity ones still go by grid.  A
   // plain-code group too small to fill the GPU takes the job-list kernel set
-  // for latency (four strips per load batch), a larger one the plans' kernel
-  // (set for bandwidth).
+  // for latency (several waves per tile, each walking a share of the strips),
+  // a larger one the plans' kernel (set for bandwidth).
   auto is_ext = [&](uint32_t i) { return sl.reqs[i].stripe->k > sl.reqs[i].stripe->p; };
   struct Group {
     const ZpPrimeEntry* pe;
@@ -325,6 +328,7 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     size_t begin, end;        // its requests: order[begin, end)
     const void* fn;
     uint32_t tile;            // bytes of a column tile
+    int per_wg, threads, lds; // launch shape
     uint32_t first, n;        // its items
   };
   struct Phase {
@@ -345,16 +349,19 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     for (size_t o = 0; o < P.order.size(); ++o) {
       const Resident* st = sl.reqs[P.order[o]].stripe;
       if (P.groups.empty() || P.groups.back().pe->p != st->p || P.groups.back().ext != is_ext(P.order[o]))
-        P.groups.push_back(Group{zp_prime_entry(st->p), is_ext(P.order[o]), o, o, nullptr, 0, 0, 0});
+        P.groups.push_back(Group{zp_prime_entry(st->p), is_ext(P.order[o]), o, o, nullptr, 0, 0, 0, 0, 0, 0});
       P.groups.back().end = o + 1;
     }
     for (Group& g : P.groups) {
       size_t tiles256 = 0;
       for (size_t o = g.begin; o < g.end; ++o)
         tiles256 += (sl.reqs[P.order[o]].stripe->row_bytes + kBatchTileBytes - 1) / kBatchTileBytes;
-      const bool small = tiles256 < kLatencyTiles;
-      g.fn = g.ext ? g.pe->group_ext_kernel : (small ? g.pe->group_lat_kernel : g.pe->group_kernel);
-      g.tile = 64u * 4u * (uint32_t)(g.ext ? g.pe->group_ext_vec : (small ? g.pe->group_lat_vec : g.pe->group_vec));
+      const bool lat = !g.ext && tiles256 < kLatencyTiles;
+      g.fn = g.ext ? g.pe->group_ext_kernel : (lat ? g.pe->group_lat_kernel : g.pe->group_kernel);
+      g.tile = 64u * 4u * (uint32_t)(g.ext ? g.pe->group_ext_vec : (lat ? g.pe->group_lat_vec : g.pe->group_vec));
+      g.per_wg = lat ? 1 : g.pe->group_per_wg;
+      g.threads = lat ? g.pe->group_lat_threads : g.pe->group_threads;
+      g.lds = lat ? g.pe->group_lat_lds : g.pe->group_lds;
     }
     if (s->cfg.persistent) {
       // 256-byte tiles of the phase's plain-code requests, in request order.
@@ -384,9 +391,8 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     for (const Group& g : P.groups) {
       GroupArgs ga{d_jobs, d_items + g.first, g.n};
       void* args[] = {(void*)&ga};
-      const int per = g.pe->group_per_wg;
-      e = hipLaunchKernel(g.fn, dim3((g.n + per - 1) / per), dim3(g.pe->group_threads), args,
-                          (size_t)g.pe->group_lds, sl.stream);
+      e = hipLaunchKernel(g.fn, dim3((g.n + g.per_wg - 1) / g.per_wg), dim3(g.threads), args, (size_t)g.lds,
+                          sl.stream);
       if (e != hipSuccess) return e;
     }
     if (P.pn == 0) continue;
@@ -429,7 +435,12 @@ void scheduler_loop(raid6c_server* s) {
     Slot& sl = *free_slot;
     sl.reqs.clear();
     const uint64_t admit0 = s->now_ns();
-    const size_t max_batch = s->cfg.plain ? 1 : (size_t)std::max(1, s->cfg.max_batch);
+    // When no batch is in flight the GPU is idle: a smaller first batch
+    // reaches it sooner, and the next ones are formed while it runs.
+    bool idle = true;
+    for (const Slot& o : s->slots) idle &= !o.busy;
+    size_t max_batch = s->cfg.plain ? 1 : (size_t)std::max(1, s->cfg.max_batch);
+    if (idle) max_batch = std::min(max_batch, kIdleBatch);
     size_t items = 0;
     std::unordered_set<uint64_t> waiting_writes;  // skipped writes: reads of them wait too
     for (auto it = s->pending.begin(); it != s->pending.end() && sl.reqs.size() < max_batch;) {
@@ -693,8 +704,10 @@ int raid6c_server_replay(raid6c_server* s, const raid6c_request* reqs, const dou
       if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
       now = s->now_ns();
     }
+    // At most 256 per critical section, so that the scheduler can start on
+    // a burst while the rest of it is still being submitted.
     std::lock_guard<std::mutex> lk(s->mu);
-    for (; i < n && due_at(i) <= now; ++i) {
+    for (size_t m = 0; i < n && m < 256 && due_at(i) <= now; ++i, ++m) {
       s->pending.push_back(Pending{reqs[i], due_at(i), i});
       s->outstanding++;
       s->stats.submitted++;

@@ -10,7 +10,8 @@
 //      each with its own geometry, one per wave;
 //   4  the same for stripes with the extended Q parity (p < k <= 2p-1);
 //   5  the job-list kernel for small batches of the request server, set for
-//      the latency of one tile rather than for bandwidth.
+//      the latency of one tile rather than for bandwidth: the waves of a
+//      work-group share one tile and split its strips.
 // Each object is compiled alone so that the code of one never shapes the
 // compiler's choices for the others; object 0 holds the dispatch entry and
 // calls into the others.
@@ -142,13 +143,15 @@ __global__ void __launch_bounds__(64 * S) zp_split_kernel(const ZpArgs a) {
 // went from 67% to 72% of peak against vec 1 with four; two strips per batch
 // measured the same); vec 1 with four above, where vec 2 spills.
 // Variant 5 is for batches too small to fill the GPU, where a request's time
-// is the time one wave takes to walk its tile through the k strips: four
-// strips per batch at every prime (a quarter of the load rounds), vec 1
-// above p = 31 (the registers that leaves).
+// is the time a wave takes to walk its tile through the strips: the S waves
+// of a work-group share one tile and each walks a contiguous S-th of the
+// strips, four at a time (tile_split, as the strided split-K kernels), with
+// the widest tile whose S partials fit in 64 KiB of LDS: vec 2 with S = 4 up
+// to p = 13, vec 1 with S = 4 up to p = 31, vec 1 with S = 2 above.
 #if defined(RAID6C_GROUP_VEC)
 constexpr int kGroupVec = RAID6C_GROUP_VEC;
 #elif RAID6C_VARIANT == 5
-constexpr int kGroupVec = kP <= 31 ? 2 : 1;
+constexpr int kGroupVec = kP <= 13 ? 2 : 1;
 #else
 constexpr int kGroupVec = kP <= 53 ? 2 : 1;
 #endif
@@ -158,6 +161,10 @@ constexpr int kGroupUnroll = RAID6C_GROUP_UNROLL;
 constexpr int kGroupUnroll = 4;
 #else
 constexpr int kGroupUnroll = (kP > 31 && kP <= 53) ? 1 : 4;
+#endif
+#if RAID6C_VARIANT == 5
+constexpr int kLatSplit = sk_lds_bytes_any(kGroupVec, 4) <= 65536 ? 4 : 2;
+static_assert(sk_lds_bytes_any(kGroupVec, kLatSplit) <= 65536, "split partials exceed 64 KiB of LDS");
 #endif
 static_assert((kVecMask & kGroupVec) != 0, "job-list vector width not built");
 
@@ -190,10 +197,23 @@ __global__ void __launch_bounds__(256) zp_group_kernel(const GroupArgs a) {
   group_item<P, false>(a, smem);
 }
 #elif RAID6C_VARIANT == 5
+// One item per work-group of kLatSplit waves (plain code).
 template <int P>
-__global__ void __launch_bounds__(256) zp_group_lat_kernel(const GroupArgs a) {
-  extern __shared__ __align__(16) uint32_t smem[];
-  group_item<P, false>(a, smem);
+__global__ void __launch_bounds__(64 * kLatSplit) zp_group_lat_kernel(const GroupArgs a) {
+  extern __shared__ __align__(16) uint32_t part[];
+  const uint32_t i = xcd_chunk(blockIdx.x, gridDim.x);
+  if (i >= a.nitems) return;   // uniform over the work-group
+  const BatchItem item = a.items[i];
+  const BatchJob& j = a.jobs[item.job];
+  const uint32_t col = item.col + (threadIdx.x & 63) * (kGroupVec * 4);
+  const ColsJob c{j.base, j.strip_stride, j.out0, j.out1, j.src, j.src_stride, j.e0, j.e1,
+                  j.row_bytes, col, (uint32_t)((P - 1) * j.row_bytes)};
+  const Case cs{j.op, j.x, j.y};
+  if (c.lines_aligned())
+    tile_split<P, kGroupVec, kGroupUnroll, kLatSplit, false>(c, j.k, cs, item.col, part);
+  else
+    tile_split<P, kGroupVec, kGroupUnroll, kLatSplit, false>(c.with_policy<kLoadPolicyShared>(), j.k, cs,
+                                                            item.col, part);
 }
 #else
 template <int P>
@@ -309,10 +329,12 @@ void RAID6C_CAT(zp_group_shape_, RAID6C_P)(ZpPrimeEntry& e) {
   e.group_lds = kP * 256 * 4;
 }
 #elif RAID6C_VARIANT == 5
-// Same launch shape as the plan's job-list kernel; its own tile width.
+// One item per work-group of kLatSplit waves; its own tile width.
 void RAID6C_CAT(zp_group_lat_shape_, RAID6C_P)(ZpPrimeEntry& e) {
   e.group_lat_kernel = (const void*)zp_group_lat_kernel<kP>;
   e.group_lat_vec = kGroupVec;
+  e.group_lat_threads = 64 * kLatSplit;
+  e.group_lat_lds = sk_lds_bytes_any(kGroupVec, kLatSplit);
 }
 #elif RAID6C_VARIANT == 4
 // Same tiles and launch shape as the plain job-list kernel (same constants).
@@ -342,7 +364,7 @@ ZpPrimeEntry make_entry() {
   ZpPrimeEntry e{kP, &launch_plain, &RAID6C_CAT(zp_launch_ext_, RAID6C_P), kVecMask,
                  {0, unroll_mask(1), unroll_mask(2), 0, unroll_mask(4)},
                  {0, split_mask(1), split_mask(2), 0, split_mask(4)},
-                 nullptr, 0, 0, 0, 0, nullptr, 0, nullptr, 0};
+                 nullptr, 0, 0, 0, 0, nullptr, 0, nullptr, 0, 0, 0};
   RAID6C_CAT(zp_group_shape_, RAID6C_P)(e);
   RAID6C_CAT(zp_group_ext_shape_, RAID6C_P)(e);
   RAID6C_CAT(zp_group_lat_shape_, RAID6C_P)(e);
