@@ -64,7 +64,10 @@ uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 // Groups of a batch with fewer 256-byte column tiles than this (a few per
 // SIMD of the GPU) run the job-list kernel set for latency.
-constexpr size_t kLatencyTiles = 4096;
+#ifndef RAID6C_LATENCY_TILES
+#define RAID6C_LATENCY_TILES 4096
+#endif
+constexpr size_t kLatencyTiles = RAID6C_LATENCY_TILES;
 
 // Largest batch formed while no other batch is in flight.
 constexpr size_t kIdleBatch = 128;
