@@ -20,6 +20,30 @@ from oracle import zp_raid as zp
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _bench_tuning():
+    """The tuning cache bench.py loads, so that each launch below runs the
+    configuration the benchmark times; the table is cleared afterwards."""
+    from paper_cs_0611109_amd import autotune as at
+    device()
+    r.raid6c_tune_clear()
+    assert at.load_cache() > 0
+    yield
+    r.raid6c_tune_clear()
+
+
+def _cached(p, op, w):
+    """The cache entry for (p, op, row-size bucket of w): the configuration a
+    launch must use."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(r.__file__), "tuned_mi355x.json")) as f:
+        for e in json.load(f)["entries"]:
+            if e["p"] == p and e["op"] == op and e["row_bytes"].bit_length() == w.bit_length():
+                return (e["vec"], e["unroll"], e["threads"], e["split"], e["order"])
+    return None
+
+
 def _fill(batch, seed, chunk=256):
     import torch
     p, k, w, n = batch.p, batch.k, batch.row_bytes, batch.nstripes
@@ -45,12 +69,29 @@ def test_config2_encode_and_rs_full_size():
     import torch
     device()
     p, k, w, n = 13, 12, 4096, 4096
-    log(f"config2 p={p} k={k} W={w} stripes={n}")
+    for op in (0, 1):
+        assert r.raid6c_tune_get(p, op, w) == _cached(p, op, w)
+    log(f"config2 p={p} k={k} W={w} stripes={n}; encode {r.raid6c_tune_get(p, 0, w)}")
     b = r.StripeBatch.empty(p, k, w, n)
     _fill(b, 2)
     b.tensor[:, k:] = 0xA5
     b.encode()
     _check_sample(b, 2)
+    # The bench's recovery: every stripe rebuilds its own pair, uniform over
+    # the 91 strip pairs (the same draws), erased strips overwritten first.
+    log(f"config2 recovery of per-stripe pairs; {r.raid6c_tune_get(p, 1, w)}")
+    orig = b.tensor.clone()
+    er = datagen.erasures(2, n, k, "any")
+    flat = b.tensor.view(n, k + 2, -1)
+    s_idx = torch.arange(n, device="cuda:0").repeat_interleave(2)
+    flat[s_idx, torch.from_numpy(er.reshape(-1).astype(np.int64)).to("cuda:0")] = 0x5A
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    b.recover(torch.from_numpy(er).to("cuda:0"), bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    assert torch.equal(b.tensor, orig)
+    _check_sample(b, 2, step=64)
+    del orig
     log("config2 RS GF(256) on the same bytes")
     b.rs_encode()
     torch.cuda.synchronize()
@@ -66,7 +107,10 @@ def test_config3_recovery_full_size():
     import torch
     device()
     p, k, w, n = 29, 28, 1024, 8192
-    log(f"config3 p={p} k={k} W={w} stripes={n}")
+    for op in (0, 1):
+        assert r.raid6c_tune_get(p, op, w) == _cached(p, op, w)
+    log(f"config3 p={p} k={k} W={w} stripes={n}; encode {r.raid6c_tune_get(p, 0, w)}, "
+        f"recovery {r.raid6c_tune_get(p, 1, w)}")
     b = r.StripeBatch.empty(p, k, w, n)
     _fill(b, 3)
     b.encode()
