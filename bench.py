@@ -532,7 +532,9 @@ def served_poisson(n=4000, seed=5):
         span = (max(c.complete_ns for c in comps) - min(c.arrival_ns for c in comps)) / 1e9
         return {"p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
                 "GBps_user": round(st.user_bytes / span / 1e9, 1), "requests_per_s": round(n / span, 1),
-                "batches": st.batches, "failed": bad}
+                "batches": st.batches, "failed": bad,
+                "host_admit_ns_per_request": round(st.admit_ns / max(1, st.completed), 1),
+                "host_launch_us_per_batch": round(st.launch_ns / 1e3 / max(1, st.batches), 1)}
 
     zero = [0.0] * n
     # Untimed warm-up of both paths (the first launch of each kernel loads it).

@@ -32,16 +32,15 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
-#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
-#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
 #include "../../include/raid6c.h"
 #include "raid6c_internal.h"
+#include "stripe_index.h"
 
 namespace raid6c {
 int fail(int code, const char* fmt, ...);
@@ -109,6 +108,7 @@ struct Slot {
   size_t cap = 0;               // bytes of h_buf and of d_mem's table area
   uint64_t counter = 0;         // value the device counter holds between runs
   std::vector<InFlight> reqs;
+  size_t items = 0;       // 256-byte column tiles of reqs (for the tables)
   uint64_t launch_ns = 0;
   bool busy = false;      // owns requests
   bool launched = false;  // its completion event has been recorded
@@ -124,8 +124,9 @@ struct raid6c_server {
   uint8_t* store = nullptr;
   uint64_t head = 0;             // next free byte (ring)
   std::deque<Resident*> fifo;    // resident stripes, oldest first
-  std::map<uint64_t, Resident*> by_off;  // the same stripes by store offset
-  std::unordered_map<uint64_t, Resident*> index;
+  StripeIndex<Resident> index{8192};  // the same stripes by id
+  std::deque<Resident> pool;     // records (stable addresses), reused through free_res
+  std::vector<Resident*> free_res;
   std::vector<Slot> slots;
   hipStream_t plain_stream = nullptr;
 
@@ -163,29 +164,38 @@ int check_request(const raid6c_request& r) {
   return RAID6C_ST_OK;
 }
 
-// Place a new stripe in the ring, evicting the oldest idle stripes as needed.
-// Returns the stripe, or nullptr when it must wait (the oldest stripe is busy)
-// or can never fit (*never = true).
+// Place a new stripe in the ring (ring_fit), evicting the oldest idle
+// stripes as needed.  Returns the stripe, or nullptr when it must wait (the
+// oldest stripe is busy) or can never fit (*never = true).
 Resident* place(raid6c_server* s, const raid6c_request& r, bool* never) {
   const uint64_t need = stripe_bytes(r.p, r.k, r.row_bytes);
   *never = need > s->cfg.store_bytes;
   if (*never) return nullptr;
   for (;;) {
-    uint64_t off = s->head;
-    if (off + need > s->cfg.store_bytes) off = 0;  // wrap
-    // The span [off, off+need) must be free of resident stripes: the stripe
-    // with the largest offset below off+need must end at or before off.
-    bool overlap = false;
-    auto it = s->by_off.lower_bound(off + need);
-    if (it != s->by_off.begin()) {
-      --it;
-      overlap = it->second->off + it->second->bytes > off;
-    }
-    if (!overlap) {
-      Resident* st = new Resident{r.stripe_id, off, need, r.p, r.k, r.row_bytes, 0, false, false, nullptr};
+    uint64_t off = 0;
+    const bool fits = ring_fit(s->head, s->fifo.empty() ? 0 : s->fifo.front()->off, s->fifo.empty(), need,
+                               s->cfg.store_bytes, &off);
+    if (fits) {
+      Resident* st;
+      if (!s->free_res.empty()) {
+        st = s->free_res.back();
+        s->free_res.pop_back();
+      } else {
+        s->pool.emplace_back();
+        st = &s->pool.back();
+      }
+      st->id = r.stripe_id;
+      st->off = off;
+      st->bytes = need;
+      st->p = r.p;
+      st->k = r.k;
+      st->row_bytes = r.row_bytes;
+      st->refs = 0;
+      st->ready = st->failed = false;
+      st->writer = nullptr;
+      st->waiters.clear();
       s->fifo.push_back(st);
-      s->by_off[off] = st;
-      s->index[r.stripe_id] = st;
+      s->index.insert(r.stripe_id, st);
       s->head = off + need;
       return st;
     }
@@ -193,9 +203,8 @@ Resident* place(raid6c_server* s, const raid6c_request& r, bool* never) {
     Resident* oldest = s->fifo.front();
     if (oldest->refs > 0) return nullptr;
     s->fifo.pop_front();
-    s->by_off.erase(oldest->off);
     s->index.erase(oldest->id);
-    delete oldest;
+    s->free_res.push_back(oldest);
     s->stats.evictions++;
   }
 }
@@ -343,12 +352,18 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
   nitems = 0;
   for (int f = 0; f < 2; ++f) {
     Phase& P = ph[f];
+    // Requests by key (largest prime first, plain code before extended),
+    // in request order within a key: one counting pass, no comparisons.
+    constexpr int kKeys = 2 * (kMaxPrime + 1);
+    uint32_t start[kKeys + 1] = {};
+    auto key = [&](uint32_t i) { return 2 * (kMaxPrime - sl.reqs[i].stripe->p) + (is_ext(i) ? 1 : 0); };
+    auto by_grid = [&](uint32_t i) { return sl.reqs[i].phase == f && (!s->cfg.persistent || is_ext(i)); };
     for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
-      if (sl.reqs[i].phase == f && (!s->cfg.persistent || is_ext(i))) P.order.push_back(i);
-    std::stable_sort(P.order.begin(), P.order.end(), [&](uint32_t x, uint32_t y) {
-      if (sl.reqs[x].stripe->p != sl.reqs[y].stripe->p) return sl.reqs[x].stripe->p > sl.reqs[y].stripe->p;
-      return !is_ext(x) && is_ext(y);
-    });
+      if (by_grid(i)) start[key(i) + 1]++;
+    for (int c = 0; c < kKeys; ++c) start[c + 1] += start[c];
+    P.order.resize(start[kKeys]);
+    for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
+      if (by_grid(i)) P.order[start[key(i)]++] = i;
     for (size_t o = 0; o < P.order.size(); ++o) {
       const Resident* st = sl.reqs[P.order[o]].stripe;
       if (P.groups.empty() || P.groups.back().pe->p != st->p || P.groups.back().ext != is_ext(P.order[o]))
@@ -415,6 +430,43 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
   return hipEventRecord(sl.done, sl.stream);
 }
 
+// Builds and launches one admitted batch (its slot busy, not launched).
+// Called with the lock held; drops it while it works and returns with it
+// held, the slot launched, or its requests failed and the slot free again.
+void launch_batch(raid6c_server* s, Slot& sl, std::unique_lock<std::mutex>& lk) {
+  const uint64_t launch0 = s->now_ns();
+  lk.unlock();
+  hipError_t e = hipSuccess;
+  bool grew = false;
+  if (!s->cfg.plain && !grow_slot(sl, sl.reqs.size(), sl.items, &grew)) e = hipErrorOutOfMemory;
+  sl.launch_ns = s->now_ns();
+  if (e == hipSuccess) e = launch_slot(s, sl);
+  lk.lock();
+  s->stats.launch_ns += s->now_ns() - launch0;
+  if (grew) s->stats.table_grows++;
+  if (e == hipSuccess) {
+    sl.launched = true;
+    s->cv_done.notify_all();
+    return;
+  }
+  s->thread_error = RAID6C_E_HIP;
+  // Fail the batch's requests so callers are not left waiting.
+  const uint64_t t = s->now_ns();
+  for (const InFlight& f : sl.reqs) {
+    f.stripe->refs--;
+    if (f.req.kind == RAID6C_REQ_WRITE) {
+      f.stripe->failed = true;
+      f.stripe->writer = nullptr;
+      release_waiters(s, f.stripe);
+    }
+    complete_one(s, f.req, f.arrival_ns, f.index, RAID6C_ST_INVALID, t, t, 0);
+  }
+  sl.reqs.clear();
+  sl.busy = false;
+  s->cv_done.notify_all();
+  s->cv_sched.notify_all();
+}
+
 void scheduler_loop(raid6c_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -456,7 +508,7 @@ void scheduler_loop(raid6c_server* s) {
         continue;
       }
       if (status == RAID6C_ST_OK && r.kind == RAID6C_REQ_WRITE) {
-        if (s->index.count(r.stripe_id)) {
+        if (s->index.find(r.stripe_id) != nullptr) {
           status = RAID6C_ST_DUPLICATE;
         } else {
           bool never = false;
@@ -465,11 +517,10 @@ void scheduler_loop(raid6c_server* s) {
           else if (st == nullptr) wait = true;
         }
       } else if (status == RAID6C_ST_OK) {
-        auto f = s->index.find(r.stripe_id);
-        if (f == s->index.end()) {
+        st = s->index.find(r.stripe_id);
+        if (st == nullptr) {
           status = RAID6C_ST_NOT_RESIDENT;
         } else {
-          st = f->second;
           if (st->failed || classify(st->k, r.e0, r.e1).op == OP_BAD || r.dst == nullptr ||
               ((uintptr_t)r.dst & 15u) != 0) {
             status = RAID6C_ST_INVALID;
@@ -508,39 +559,10 @@ void scheduler_loop(raid6c_server* s) {
       continue;
     }
     sl.busy = true;
+    sl.items = items;
     s->stats.batches++;
-    const uint64_t launch0 = s->now_ns();
-    s->stats.admit_ns += launch0 - admit0;
-    lk.unlock();
-    hipError_t e = hipSuccess;
-    bool grew = false;
-    if (!s->cfg.plain && !grow_slot(sl, sl.reqs.size(), items, &grew)) e = hipErrorOutOfMemory;
-    sl.launch_ns = s->now_ns();
-    if (e == hipSuccess) e = launch_slot(s, sl);
-    lk.lock();
-    s->stats.launch_ns += s->now_ns() - launch0;
-    if (grew) s->stats.table_grows++;
-    if (e == hipSuccess) {
-      sl.launched = true;
-      s->cv_done.notify_all();
-    }
-    if (e != hipSuccess) {
-      s->thread_error = RAID6C_E_HIP;
-      // Fail the batch's requests so callers are not left waiting.
-      const uint64_t t = s->now_ns();
-      for (const InFlight& f : sl.reqs) {
-        f.stripe->refs--;
-        if (f.req.kind == RAID6C_REQ_WRITE) {
-          f.stripe->failed = true;
-          f.stripe->writer = nullptr;
-          release_waiters(s, f.stripe);
-        }
-        complete_one(s, f.req, f.arrival_ns, f.index, RAID6C_ST_INVALID, t, t, 0);
-      }
-      sl.reqs.clear();
-      sl.busy = false;
-      s->cv_done.notify_all();
-    }
+    s->stats.admit_ns += s->now_ns() - admit0;
+    launch_batch(s, sl, lk);
   }
 }
 
@@ -625,6 +647,12 @@ int raid6c_server_create(const raid6c_server_config* cfg, raid6c_server** out) {
                 hipGetErrorString(me));
   }
   s->slots.resize((size_t)cfg->max_inflight);
+  // Stripe records for the first few thousand writes, touched now rather
+  // than on the first burst.
+  for (int i = 0; i < 4096; ++i) {
+    s->pool.emplace_back();
+    s->free_res.push_back(&s->pool.back());
+  }
   hipError_t e = hipSuccess;
   if (cfg->plain) e = hipStreamCreateWithFlags(&s->plain_stream, hipStreamNonBlocking);
   for (Slot& sl : s->slots) {
@@ -726,10 +754,10 @@ int raid6c_server_replay(raid6c_server* s, const raid6c_request* reqs, const dou
 int raid6c_server_stripe(raid6c_server* s, uint64_t stripe_id, void** base, uint64_t* strip_stride) {
   if (s == nullptr || base == nullptr || strip_stride == nullptr) return fail(RAID6C_E_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  auto f = s->index.find(stripe_id);
-  if (f == s->index.end()) return fail(RAID6C_E_ARG, "stripe %llu is not resident", (unsigned long long)stripe_id);
-  *base = s->store + f->second->off;
-  *strip_stride = (uint64_t)(f->second->p - 1) * f->second->row_bytes;
+  const Resident* f = s->index.find(stripe_id);
+  if (f == nullptr) return fail(RAID6C_E_ARG, "stripe %llu is not resident", (unsigned long long)stripe_id);
+  *base = s->store + f->off;
+  *strip_stride = (uint64_t)(f->p - 1) * f->row_bytes;
   return RAID6C_OK;
 }
 
@@ -763,7 +791,6 @@ int raid6c_server_destroy(raid6c_server* s) {
     for (uint8_t* d : sl.retired_d) (void)hipFree(d);
   }
   if (s->plain_stream) (void)hipStreamDestroy(s->plain_stream);
-  for (Resident* r : s->fifo) delete r;
   if (s->store) (void)hipFree(s->store);
   delete s;
   return RAID6C_OK;
