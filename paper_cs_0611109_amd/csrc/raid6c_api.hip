@@ -437,10 +437,16 @@ int raid6c_rs_encode_n(int k, size_t strip_bytes, void* base, size_t strip_strid
 static int launch_update(int p, UpdArgs a, size_t nstripes, void* stream) {
   if (nstripes == 0) return RAID6C_OK;
   const int vec = (p <= 13 && a.row_bytes >= 512) ? 2 : 1;
+#ifndef RAID6C_UPDATE_THREADS
+#define RAID6C_UPDATE_THREADS 128
+#endif
   int threads = 64;
-  while (threads < 128 && (uint64_t)threads * vec * 4 < a.row_bytes) threads *= 2;
+  while (threads < RAID6C_UPDATE_THREADS && (uint64_t)threads * vec * 4 < a.row_bytes) threads *= 2;
   const uint64_t tile_bytes = (uint64_t)threads * vec * 4;
   a.tiles = (uint32_t)((a.row_bytes + tile_bytes - 1) / tile_bytes);
+  const uint64_t addr_bits = a.row_bytes | (uintptr_t)a.base | a.strip_stride | a.stripe_stride |
+                             (uintptr_t)a.src | a.src_stride | (uintptr_t)a.pd | (uintptr_t)a.pp | (uintptr_t)a.pq;
+  const bool shared_lines = (addr_bits & 127u) != 0;
   const uint64_t chunk = (((uint64_t)1 << 31) / threads) / a.tiles;
   size_t done = 0;
   while (done < nstripes) {
@@ -452,7 +458,8 @@ static int launch_update(int p, UpdArgs a, size_t nstripes, void* stream) {
       if (a.targets != nullptr) b.targets = a.targets + done;
     }
     b.nstripes = (uint32_t)n;
-    const hipError_t err = update_launch(b, p, vec, threads, (uint32_t)(n * a.tiles), (hipStream_t)stream);
+    const hipError_t err =
+        update_launch(b, p, vec, threads, (uint32_t)(n * a.tiles), shared_lines, (hipStream_t)stream);
     if (err != hipSuccess) return fail(RAID6C_E_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     done += n;
   }

@@ -234,7 +234,10 @@ struct UpdArgs {
   int32_t t;
   int32_t k;
 };
-hipError_t update_launch(const UpdArgs& a, int p, int vec, int threads, uint32_t grid, hipStream_t stream);
+// shared_lines: rows not all on 128-byte lines (ordinary-policy loads,
+// XCD-chunked work-group order).
+hipError_t update_launch(const UpdArgs& a, int p, int vec, int threads, uint32_t grid, bool shared_lines,
+                         hipStream_t stream);
 
 // Horizontal Z_17 layout <-> vertical strips (layout.hip): count strips of
 // 8*row_bytes 16-bit words <-> count strips of 16 rows of row_bytes bytes.

@@ -10,7 +10,10 @@
 //
 // Grid: one work-group per (stripe, column tile); each thread owns V dwords
 // of every row.  The data-dependent rotation of dD goes through the
-// thread's LDS column, one dword column at a time.
+// thread's LDS column, one dword column at a time.  Rows that do not all
+// start on 128-byte lines (SHARED) load with the ordinary cache policy and
+// take the XCD-chunked work-group order, as the encode and recovery kernels
+// do: a line at the edge of two tiles is then fetched once into one L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,14 +24,43 @@ namespace raid6c {
 
 namespace {
 
-template <int P, int V>
+template <int P, int V, bool SHARED>
 __global__ void __launch_bounds__(256) update_kernel(const UpdArgs a) {
   typedef typename vec_t<V>::type VT;
   typedef comp<V> CP;
   constexpr int R = P - 1;
+  constexpr int LP = SHARED ? kLoadPolicyShared : RAID6C_LOAD_POLICY;
   extern __shared__ __align__(16) uint32_t smem[];
-  const uint32_t stripe = blockIdx.x / a.tiles;
-  const uint32_t tile = blockIdx.x - stripe * a.tiles;
+  const uint32_t b = SHARED ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
+  const uint32_t stripe = b / a.tiles;
+  const uint32_t tile = b - stripe * a.tiles;
+  const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
+  const uint64_t W = a.row_bytes;
+  const uint32_t nb = (uint32_t)(R * W);
+  uint8_t *sb = nullptr, *pp, *pq;
+  if (a.base != nullptr) {
+    sb = a.base + (uint64_t)stripe * a.stripe_stride;
+    pp = sb + (uint64_t)a.k * a.strip_stride;
+    pq = sb + (uint64_t)(a.k + 1) * a.strip_stride;
+  } else {
+    pp = a.pp;
+    pq = a.pq;
+  }
+  const __amdgpu_buffer_rsrc_t bp = make_rsrc(pp, nb), bq = make_rsrc(pq, nb);
+  const __amdgpu_buffer_rsrc_t bn = make_rsrc(a.src + (uint64_t)stripe * a.src_stride, nb);
+  const bool live = col < a.row_bytes;
+
+  // The new strip, P and Q do not depend on which strip is replaced: their
+  // loads go out first, while the target index is still on its way.
+  VT n[R], pr[R], q[R];
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) n[r] = ld<VT, LP>(bn, r, W, col);
+#pragma unroll
+    for (int r = 0; r < R; ++r) pr[r] = ld<VT, LP>(bp, r, W, col);
+#pragma unroll
+    for (int r = 0; r < R; ++r) q[r] = ld<VT, LP>(bq, r, W, col);
+  }
   int t = a.t;
   if (a.targets != nullptr) t = a.targets[stripe];
   t = __builtin_amdgcn_readfirstlane(t);
@@ -36,31 +68,13 @@ __global__ void __launch_bounds__(256) update_kernel(const UpdArgs a) {
     if (tile == 0 && threadIdx.x == 0 && a.bad_count != nullptr) atomicAdd(a.bad_count, 1);
     return;
   }
-  const uint32_t col = (tile * blockDim.x + threadIdx.x) * (V * 4);
-  if (col >= a.row_bytes) return;
-  const uint64_t W = a.row_bytes;
-  const uint32_t nb = (uint32_t)(R * W);
-  uint8_t *pd, *pp, *pq;
-  if (a.base != nullptr) {
-    uint8_t* sb = a.base + (uint64_t)stripe * a.stripe_stride;
-    pd = sb + (uint64_t)t * a.strip_stride;
-    pp = sb + (uint64_t)a.k * a.strip_stride;
-    pq = sb + (uint64_t)(a.k + 1) * a.strip_stride;
-  } else {
-    pd = a.pd;
-    pp = a.pp;
-    pq = a.pq;
-  }
-  const __amdgpu_buffer_rsrc_t bd = make_rsrc(pd, nb), bp = make_rsrc(pp, nb), bq = make_rsrc(pq, nb);
-  const __amdgpu_buffer_rsrc_t bn = make_rsrc(a.src + (uint64_t)stripe * a.src_stride, nb);
+  if (!live) return;
+  uint8_t* pd = sb != nullptr ? sb + (uint64_t)t * a.strip_stride : a.pd;
+  const __amdgpu_buffer_rsrc_t bd = make_rsrc(pd, nb);
 
-  VT d[R], n[R], pr[R];
+  VT d[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) d[r] = ld<VT>(bd, r, W, col);
-#pragma unroll
-  for (int r = 0; r < R; ++r) n[r] = ld<VT>(bn, r, W, col);
-#pragma unroll
-  for (int r = 0; r < R; ++r) pr[r] = ld<VT>(bp, r, W, col);
+  for (int r = 0; r < R; ++r) d[r] = ld<VT, LP>(bd, r, W, col);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -68,9 +82,6 @@ __global__ void __launch_bounds__(256) update_kernel(const UpdArgs a) {
     st<VT>(bd, r, W, col, n[r]);
     st<VT>(bp, r, W, col, pr[r] ^ d[r]);
   }
-  VT q[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) q[r] = ld<VT>(bq, r, W, col);
   // g_t dD: rotation by s of the lift of dD in C, reduced (row r plus the
   // row that lands on p-1); plus dD itself for an extended strip.
   const bool ext = t >= P;
@@ -96,26 +107,33 @@ __global__ void __launch_bounds__(256) update_kernel(const UpdArgs a) {
   for (int r = 0; r < R; ++r) st<VT>(bq, r, W, col, q[r]);
 }
 
-template <int P>
-hipError_t launch_p(const UpdArgs& a, int vec, int threads, uint32_t grid, hipStream_t stream) {
+template <int P, bool SHARED>
+hipError_t launch_ps(const UpdArgs& a, int vec, int threads, uint32_t grid, hipStream_t stream) {
   const size_t lds = (size_t)P * threads * 4;
   if (vec == 1) {
-    hipLaunchKernelGGL((update_kernel<P, 1>), dim3(grid), dim3(threads), lds, stream, a);
+    hipLaunchKernelGGL((update_kernel<P, 1, SHARED>), dim3(grid), dim3(threads), lds, stream, a);
   } else if (vec == 2 && P <= 31) {
-    hipLaunchKernelGGL((update_kernel<P, (P <= 31 ? 2 : 1)>), dim3(grid), dim3(threads), lds, stream, a);
+    hipLaunchKernelGGL((update_kernel<P, (P <= 31 ? 2 : 1), SHARED>), dim3(grid), dim3(threads), lds, stream, a);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <int P>
+hipError_t launch_p(const UpdArgs& a, int vec, int threads, uint32_t grid, bool shared_lines, hipStream_t stream) {
+  return shared_lines ? launch_ps<P, true>(a, vec, threads, grid, stream)
+                      : launch_ps<P, false>(a, vec, threads, grid, stream);
+}
+
 }  // namespace
 
-hipError_t update_launch(const UpdArgs& a, int p, int vec, int threads, uint32_t grid, hipStream_t stream) {
+hipError_t update_launch(const UpdArgs& a, int p, int vec, int threads, uint32_t grid, bool shared_lines,
+                         hipStream_t stream) {
   switch (p) {
 #define RAID6C_UPD(q) \
   case q:             \
-    return launch_p<q>(a, vec, threads, grid, stream);
+    return launch_p<q>(a, vec, threads, grid, shared_lines, stream);
     RAID6C_UPD(3) RAID6C_UPD(5) RAID6C_UPD(7) RAID6C_UPD(11) RAID6C_UPD(13) RAID6C_UPD(17) RAID6C_UPD(19)
     RAID6C_UPD(23) RAID6C_UPD(29) RAID6C_UPD(31) RAID6C_UPD(37) RAID6C_UPD(41) RAID6C_UPD(43) RAID6C_UPD(47)
     RAID6C_UPD(53) RAID6C_UPD(59) RAID6C_UPD(61)
