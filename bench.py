@@ -701,10 +701,11 @@ def batched_mixed(reps, stream):
         tuned_ms = r.raid6c_plan_autotune(plan, reps=2)
         sched = r.raid6c_plan_get_schedule(plan)
         plan_ms = time_launches(lambda: r.raid6c_plan_run(plan), reps, stream)
-        # Both execution modes on their own, for the record.
+        # Both execution modes on their own, for the record (the persistent
+        # kernel with 8 single-wave work-groups per CU, one item per pop).
         modes = {}
         for name, cand in (("grouped_chained", (8, 4, 0, 2)), ("grouped_side_by_side", (8, 4, 0, 1)),
-                           ("persistent", (8, 4, 0, 0))):
+                           ("persistent", (8, 1, 0, 0))):
             r.raid6c_plan_set_schedule(plan, *cand)
             ms_m = time_launches(lambda: r.raid6c_plan_run(plan), max(3, reps // 2), stream)
             modes[name] = round(sum(ms_m) / len(ms_m), 3)
