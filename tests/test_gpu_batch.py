@@ -116,10 +116,11 @@ def test_plan_after_autotune():
 
 def test_plan_rows_on_cache_lines():
     """Rows, strides and stripes on 128-byte lines (non-temporal loads) and,
-    in the same plan's second half, rows 16 bytes past them (ordinary loads)."""
+    in the same plan's second half, rows 16 bytes past them (ordinary loads),
+    through the chained job-list grids and through the persistent kernel."""
     specs = [(p, k, 128 * m, e) for (p, k, w, e), m in zip(_mixed_jobs(4, 40), [1, 2, 3, 5, 8] * 8)]
     specs = [s if i < 20 else (s[0], s[1], s[2] + 16, s[3]) for i, s in enumerate(specs)]
-    _run_plan(specs, seed=25, align=128)
+    _run_plan(specs, seed=25, align=128, schedules=[(8, 4, 0, 2), (8, 1, 0)])
 
 
 def test_plan_every_case_large_prime():
