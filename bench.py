@@ -601,19 +601,33 @@ def served_poisson(n=4000, seed=5):
     times = [t / rate for t in base_t]
     high = 4.0 * sat_plain["requests_per_s"]
     _SERVED_SAMPLES.append(("payloads", (reqs, payloads)))
-    return {"requests": n, "writes": sum(q.kind == "write" for q in reqs),
-            "saturation_plain": sat_plain, "saturation_served": sat_served,
-            "qps": round(rate, 1), "served_at_qps": run(False, times, "served_at_qps"),
-            "plain_at_qps": run(True, times, "plain_at_qps"),
-            "qps_4x_plain_saturation": round(high, 1),
-            "served_at_4x": run(False, [t / high for t in base_t], "served_at_4x"),
-            "verified_against_oracle": None}
+    out = {"requests": n, "writes": sum(q.kind == "write" for q in reqs),
+           "saturation_plain": sat_plain, "saturation_served": sat_served,
+           "qps": round(rate, 1), "served_at_qps": run(False, times, "served_at_qps"),
+           "plain_at_qps": run(True, times, "plain_at_qps"),
+           "qps_4x_plain_saturation": round(high, 1),
+           "served_at_4x": run(False, [t / high for t in base_t], "served_at_4x"),
+           "verified_against_oracle": None}
+    # Latency against load, from the plain path's saturation rate R up to
+    # the served path's own saturation (about 60 R).
+    sweep = []
+    for mult in SERVE_SWEEP:
+        q_ = mult * sat_plain["requests_per_s"]
+        res = run(False, [t / q_ for t in base_t], None)
+        sweep.append({"x_plain_saturation": mult, "qps": round(q_, 1),
+                      **{k: res[k] for k in ("p50_ms", "p99_ms", "GBps_user", "requests_per_s", "batches",
+                                             "failed")}})
+    out["sweep"] = sweep
+    return out
 
 
 # Server configuration of the served runs: one slot per hardware queue of
 # the process (4), up to 1024 requests per batch (at 0.8 R batches hold one
 # or two requests; a backlog is taken in large batches).
 SERVE_INFLIGHT, SERVE_MAX_BATCH = 4, 1024
+# Offered loads of the served sweep, in multiples of the plain path's
+# saturation rate.
+SERVE_SWEEP = (1, 2, 8, 16, 32, 64)
 
 # (run name, [(request index, host bytes or None)]) of the last served_poisson
 # call, and ("payloads", (requests, {write index: data strips})).
