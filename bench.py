@@ -748,6 +748,24 @@ def batched_mixed(reps, stream):
     }
 
 
+def copy_ceiling(stream, nbytes=2 << 30, reps=10):
+    """The bandwidth a plain device-to-device copy reaches (the runtime's own
+    copy kernel, read and write 1:1), as context for the roofline: the Z_p
+    kernels read 6 to 14 bytes per byte written."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    a.random_(0, 256)
+    b = torch.empty_like(a)
+    ms = time_launches(lambda: b.copy_(a), reps, stream)
+    med = pct(ms, 50)
+    del a, b
+    torch.cuda.empty_cache()
+    moved = 2 * nbytes
+    return {"kind": "device-to-device copy, 2 GiB each way", "ms_p50": round(med, 4),
+            "GBps_moved": round(moved / (med / 1e3) / 1e9, 1),
+            "frac_of_peak": round(moved / (med / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}
+
+
 def copy_probe(stream, nbytes=1 << 30, reps=3):
     """Plain device copies of a known size (to scale HBM byte counters)."""
     import torch
@@ -1411,6 +1429,8 @@ def main():
         "autotune": tuned,
     }
     if not args.no_extras:
+        log("HBM ceiling of a plain device copy")
+        result["hbm_ceiling"] = copy_ceiling(stream)
         log(f"recovery at p={P3} k={K3} W={W3} x {N3} stripes, by erasure class")
         result["recover_config3"] = config3(max(20, args.steps), stream)
         log("launch latency at p=5 k=4 W=64 x 1024 stripes")
