@@ -1428,6 +1428,12 @@ def main():
         "roofline": roofline,
         "autotune": tuned,
     }
+    # The paper's own speeds, quoted (not re-run), with the processor it names.
+    result["paper_reference"] = {
+        "processor": "2.8 GHz Intel Pentium 4",
+        "syndrome_generation_MBps": {"linux_rs_sse2x2": 2702, "z17_sse2x2": 3160},
+        "source": "Section 4.5, syndrome-generation speed table (fastest routines)",
+        "this_encode_over_paper_z17": round(result["encode"]["GBps_user"] * 1e3 / 3160, 1)}
     if not args.no_extras:
         log("HBM ceiling of a plain device copy")
         result["hbm_ceiling"] = copy_ceiling(stream)
