@@ -405,8 +405,9 @@ int raid6c_run_jobs_noalloc(const raid6c_job* jobs, size_t njobs, void* stream);
  * the oldest stripes that no admitted request is using, and waits while the
  * oldest one is busy.  A scheduler thread admits pending requests into free
  * slots (up to max_inflight batches on their own streams, max_batch requests
- * each) and launches each batch as one job-list grid per prime (or one
- * persistent kernel, `persistent`); requests arriving
+ * each) and launches each batch as one job-list grid per prime (small groups
+ * of the primes up to 31 in one grid together), or as one persistent kernel
+ * (`persistent`); requests arriving
  * meanwhile go into the next free slot, so batches overlap on the device.  A
  * completion thread reports each request with its arrival, launch and
  * completion times (ns on the server's steady clock).  With `plain` set,

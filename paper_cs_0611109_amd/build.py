@@ -32,7 +32,7 @@ CFLAGS = [
 
 # Plain (non-templated-per-prime) sources.
 SOURCES = ["raid6c_api.hip", "tune.hip", "rs_kernels.hip", "update.hip", "layout.hip", "batch.hip", "serve.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "zp_multi.hip"]
 
 
 def _units(build_dir):

@@ -9,8 +9,10 @@
 //
 // A scheduler thread admits pending requests into free "slots" (a stream, an
 // event and job/item tables) and launches each slot's requests as one grid
-// of the job-list kernel per prime present (a plan's grouped schedule), or,
-// with `persistent` set, as one persistent kernel (batch.hip); requests that arrive
+// of the job-list kernel per prime present (a plan's grouped schedule; small
+// groups of the primes up to 31 share one grid of the multi-prime kernel,
+// zp_multi.hip), or, with `persistent` set, as one persistent kernel
+// (batch.hip); requests that arrive
 // while slots are busy are admitted into the next free slot, so up to
 // max_inflight batches overlap on the device.  A completion thread polls the
 // slots' events, stamps completion times and releases stripes.  With
@@ -41,6 +43,7 @@
 #include "../../include/raid6c.h"
 #include "raid6c_internal.h"
 #include "stripe_index.h"
+#include "zp_multi.h"
 
 namespace raid6c {
 int fail(int code, const char* fmt, ...);
@@ -70,6 +73,12 @@ constexpr size_t kLatencyTiles = RAID6C_LATENCY_TILES;
 
 // Largest batch formed while no other batch is in flight.
 constexpr size_t kIdleBatch = 128;
+
+// Small groups of primes up to kMultiMaxPrime share one grid per phase.
+#ifndef RAID6C_SERVE_MULTI
+#define RAID6C_SERVE_MULTI 1
+#endif
+constexpr bool kMultiGrids = RAID6C_SERVE_MULTI != 0;
 
 struct Pending {
   raid6c_request req;
@@ -406,12 +415,31 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
   for (const InFlight& f : sl.reqs) max_p = std::max(max_p, f.stripe->p);
   for (int f = 0; f < 2; ++f) {
     const Phase& P = ph[f];
-    for (const Group& g : P.groups) {
-      GroupArgs ga{d_jobs, d_items + g.first, g.n};
-      void* args[] = {(void*)&ga};
-      e = hipLaunchKernel(g.fn, dim3((g.n + g.per_wg - 1) / g.per_wg), dim3(g.threads), args, (size_t)g.lds,
-                          sl.stream);
+    // Consecutive groups of primes up to kMultiMaxPrime that take the
+    // latency kernel run as one grid of the multi-prime kernel: grids on a
+    // stream run one after another, and these are each too small to fill
+    // the GPU.  Their items are contiguous and their tiles the same width.
+    auto multi_ok = [&](const Group& g) { return g.fn == g.pe->group_lat_kernel && g.pe->p <= kMultiMaxPrime; };
+    for (size_t gi = 0; gi < P.groups.size();) {
+      const Group& g = P.groups[gi];
+      size_t end = gi + 1;
+      if (kMultiGrids && multi_ok(g))
+        while (end < P.groups.size() && multi_ok(P.groups[end])) ++end;
+      if (end - gi > 1) {
+        const uint32_t n = P.groups[end - 1].first + P.groups[end - 1].n - g.first;
+        int lds = 0;   // the largest need of the primes present (vec 2 stops at p = 13)
+        for (size_t m = gi; m < end; ++m) lds = std::max(lds, zp_multi_lds(P.groups[m].pe->p));
+        GroupArgs ga{d_jobs, d_items + g.first, n};
+        void* args[] = {(void*)&ga};
+        e = hipLaunchKernel(zp_multi_kernel(), dim3(n), dim3(256), args, (size_t)lds, sl.stream);
+      } else {
+        GroupArgs ga{d_jobs, d_items + g.first, g.n};
+        void* args[] = {(void*)&ga};
+        e = hipLaunchKernel(g.fn, dim3((g.n + g.per_wg - 1) / g.per_wg), dim3(g.threads), args, (size_t)g.lds,
+                            sl.stream);
+      }
       if (e != hipSuccess) return e;
+      gi = end;
     }
     if (P.pn == 0) continue;
     // One persistent kernel over the phase's plain-code requests.
