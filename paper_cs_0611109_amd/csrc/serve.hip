@@ -419,7 +419,10 @@ hipError_t launch_slot(raid6c_server* s, Slot& sl) {
     // latency kernel run as one grid of the multi-prime kernel: grids on a
     // stream run one after another, and these are each too small to fill
     // the GPU.  Their items are contiguous and their tiles the same width.
-    auto multi_ok = [&](const Group& g) { return g.fn == g.pe->group_lat_kernel && g.pe->p <= kMultiMaxPrime; };
+    auto multi_ok = [&](const Group& g) {
+      return g.fn == g.pe->group_lat_kernel && g.pe->p <= kMultiMaxPrime &&
+             g.tile == 256u * (uint32_t)zp_multi_vec(g.pe->p);
+    };
     for (size_t gi = 0; gi < P.groups.size();) {
       const Group& g = P.groups[gi];
       size_t end = gi + 1;
