@@ -118,6 +118,28 @@ def test_served_results_match_oracle(persistent):
         r.raid6c_server_destroy(srv)
 
 
+def test_every_prime_up_to_31_in_shared_grids_matches_oracle():
+    """Writes and degraded reads over every prime up to 31, small enough
+    that each batch's groups of these primes run as one grid of the
+    multi-prime kernel (every case of its switch), checked against the
+    oracle (Lemma 3.1.2: the rebuilt strips are unique)."""
+    device()
+    primes = (3, 5, 7, 11, 13, 17, 19, 23, 29, 31)
+    reqs = datagen.serve_requests(43, 500, qps=200000.0, primes=primes, pay_hi=64 << 10)
+    assert {q.p for q in reqs} == set(primes)
+    c, pay, out, out_off, data = _stage(reqs, 43)
+    stripes = _expected_stripes(reqs, data)
+    srv = r.raid6c_server_create(4 << 30, max_inflight=4, max_batch=128)
+    try:
+        comps = r.raid6c_server_replay(srv, c, [q.arrival_s for q in reqs])
+        _check(srv, reqs, comps, out, out_off, stripes)
+        st = r.raid6c_server_get_stats(srv)
+        log(f"{st.batches} batches for {len(reqs)} requests")
+        assert st.batches < len(reqs)
+    finally:
+        r.raid6c_server_destroy(srv)
+
+
 def test_alone_and_in_the_mix_are_identical():
     import torch
     device()
