@@ -1304,7 +1304,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (stripes are independent, "
-              "so more GPUs would shard stripes with no communication; see the design notes).",
+              "so more GPUs would each take a share of the stripes, with no communication between them).",
               file=sys.stderr)
         sys.exit(2)
     # The CPU oracle over every core runs first, in worker processes started
