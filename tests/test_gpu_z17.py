@@ -33,10 +33,16 @@ def test_conversion_matches_oracle(w, count):
     out_v.fill_(0x5A)
     r.raid6c_z17_to_vertical(to_dev(words.view(np.int16)), w, count, out_v)
     assert np.array_equal(to_host(out_v), want_v)
-    out_h = torch.empty((count, 8 * w), dtype=torch.int16, device="cuda:0")
-    out_h.fill_(0x5A5A)
+    # 4 KiB past the output must stay untouched (the last work-group may be
+    # partial).
+    guard = 2048
+    out_g = torch.empty(count * 8 * w + guard, dtype=torch.int16, device="cuda:0")
+    out_g.fill_(0x5A5A)
+    out_h = out_g[:count * 8 * w].view(count, 8 * w)
     r.raid6c_z17_to_horizontal(out_v, w, count, out_h)
-    assert np.array_equal(to_host(out_h).view(np.uint16), words)
+    got = to_host(out_g).view(np.uint16)
+    assert np.array_equal(got[:count * 8 * w].reshape(count, 8 * w), words)
+    assert np.all(got[count * 8 * w:] == 0x5A5A)
 
 
 def test_pipeline_equals_packed_encode():
