@@ -1279,6 +1279,10 @@ def main():
                     help="write the profiles/ summary of a --p29-profile run (no GPU needed)")
     ap.add_argument("--summarize-p29-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ HBM-byte summary of the two --p29-profile counter runs (no GPU needed)")
+    ap.add_argument("--config", type=int, choices=(1, 2, 3, 4, 5),
+                    help="measure one workload only and print its JSON object: 1 launch latency at p=5, "
+                         "2 the headline step (no extras), 3 p=29 recovery by class, 4 the 20,000-stripe plan, "
+                         "5 the served stream")
     ap.add_argument("--rows-probe", action="store_true",
                     help="only the encodes of rows on / off 128-byte lines (for the byte counters)")
     ap.add_argument("--summarize-rows", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -1310,7 +1314,10 @@ def main():
     # The CPU oracle over every core runs first, in worker processes started
     # before torch is imported and before anything touches the GPU.
     parallel = None
-    if not (args.no_cpu_baseline or args.plan_profile or args.p29_profile or args.rows_probe):
+    if args.config == 2:
+        args.no_extras = True
+    if not (args.no_cpu_baseline or args.plan_profile or args.p29_profile or args.rows_probe or
+            args.config not in (None, 2)):
         log("cpu baseline: oracle on every core (worker processes, before the GPU is touched)")
         parallel = cpu_oracle_parallel(max(1.0, args.cpu_seconds / 8))
 
@@ -1341,6 +1348,19 @@ def main():
         from paper_cs_0611109_amd import autotune as at
         at.load_cache()
         print(json.dumps(rows_probe(stream)), flush=True)
+        return
+    if args.config not in (None, 2):
+        from paper_cs_0611109_amd import autotune as at
+        at.load_cache()
+        if args.config == 1:
+            res = config1_latency(50, stream)
+        elif args.config == 3:
+            res = config3(max(20, args.steps), stream)
+        elif args.config == 4:
+            res = batched_mixed(max(10, args.steps // 2), stream)
+        else:
+            res = {"served_poisson": served_poisson(), "served_sustained_saturation": served_sustained()}
+        print(json.dumps({"config": args.config, "result": res}), flush=True)
         return
 
     log(f"allocating and filling p={P} k={K} W={W} x {NSTRIPES} stripes")
