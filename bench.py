@@ -906,6 +906,104 @@ def plan_profile(runs):
     return {"plan_runs": runs, "plan_ms_mean": round(sum(ms) / len(ms), 3)}
 
 
+SERVE_PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_serve -o run -- "
+                     "python -u bench.py --serve-profile 3")
+
+
+def serve_profile(runs):
+    """The served stream's 4000 requests, all due at t = 0, replayed `runs`
+    times into a fresh server each (after one untimed warm-up replay), for
+    the profiler: the saturated case, where batches overlap most."""
+    import time
+
+    import datagen
+    import paper_cs_0611109_amd as r
+    reqs = datagen.serve_requests(5, 4000, qps=1.0)
+    arr, pay, outb, _, _ = _stage_served(reqs)
+    out = []
+    for i in range(runs + 1):
+        srv = r.raid6c_server_create(8 << 30, max_inflight=SERVE_INFLIGHT, max_batch=SERVE_MAX_BATCH)
+        try:
+            comps = r.raid6c_server_replay(srv, arr, [0.0] * len(reqs))
+            st = r.raid6c_server_get_stats(srv)
+        finally:
+            r.raid6c_server_destroy(srv)
+        span = (max(c.complete_ns for c in comps) - min(c.arrival_ns for c in comps)) / 1e9
+        if i > 0:
+            out.append({"GBps_user": round(st.user_bytes / span / 1e9, 1), "batches": st.batches,
+                        "failed": sum(c.status != r.RAID6C_ST_OK for c in comps)})
+        time.sleep(0.02)   # a gap that separates the runs in the trace
+    del pay, outb
+    return {"serve_runs": out, "user_bytes_per_run": sum(q.k * (q.p - 1) * q.row_bytes for q in reqs)}
+
+
+def summarize_serve_profile(stats_dir: str, out_dir: str = None) -> dict:
+    """Summary of a SERVE_PROFILE_CMD run (host-only): per run, the span
+    from the first grid's start to the last grid's end, the time the GPU had
+    a grid running, and per kernel the grids and their mean duration."""
+    import re
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    import datagen
+    reqs = datagen.serve_requests(5, 4000, qps=1.0)
+    user = sum(q.k * (q.p - 1) * q.row_bytes for q in reqs)
+    rows = [t for t in _read_csv(os.path.join(stats_dir, "run_kernel_trace.csv")) if "zp_" in t["Kernel_Name"]]
+    rows.sort(key=lambda t: int(t["Start_Timestamp"]))
+    runs = [[rows[0]]]
+    for a, b in zip(rows, rows[1:]):
+        if int(b["Start_Timestamp"]) - int(a["End_Timestamp"]) > 3_000_000:
+            runs.append([])
+        runs[-1].append(b)
+    runs = runs[1:]                    # the first is the warm-up replay
+    if not runs:
+        raise RuntimeError(f"{stats_dir}: no timed replay found after the warm-up")
+
+    def name(k):
+        m = re.search(r"(zp_\w+_kernel)(<(\d+)>)?", k)
+        return m.group(1) + (f"<{m.group(3)}>" if m.group(3) else "")
+
+    lines = ["# rocprofv3 kernel trace: served stream, 4000 requests (60% writes, 40% degraded reads; p from "
+             "{11,13,29,37}, k = p-1,",
+             "# payloads log-uniform over 4 KiB..4 MiB) all due at t = 0 (saturation), 4 slots, up to 1024 "
+             "requests per batch",
+             "# command (from the repository root, on one MI355X):", "#   " + SERVE_PROFILE_CMD,
+             "# source: run_kernel_trace.csv; runs separated by idle gaps; the first (warm-up) run is left out",
+             f"# user data per run: {user} B", ""]
+    res = {"runs": []}
+    per_kernel = {}
+    for i, run in enumerate(runs):
+        t0 = min(int(t["Start_Timestamp"]) for t in run)
+        t1 = max(int(t["End_Timestamp"]) for t in run)
+        busy, cur = 0, None
+        for t in sorted(run, key=lambda t: int(t["Start_Timestamp"])):
+            s_, e_ = int(t["Start_Timestamp"]), int(t["End_Timestamp"])
+            if cur is None or s_ > cur[1]:
+                if cur:
+                    busy += cur[1] - cur[0]
+                cur = [s_, e_]
+            else:
+                cur[1] = max(cur[1], e_)
+        busy += cur[1] - cur[0]
+        streams = {t["Stream_Id"] for t in run}
+        lines.append(f"run {i + 1}: {len(run)} grids on {len(streams)} streams; span {(t1 - t0) / 1e3:.1f} us, "
+                     f"a grid running {busy / (t1 - t0):.1%} of it; {user / (t1 - t0):.1f} GB/s of user data "
+                     "over the span")
+        res["runs"].append({"grids": len(run), "span_us": round((t1 - t0) / 1e3, 1),
+                            "busy_frac": round(busy / (t1 - t0), 4), "GBps_user": round(user / (t1 - t0), 1)})
+        for t in run:
+            per_kernel.setdefault(name(t["Kernel_Name"]), []).append(
+                (int(t["End_Timestamp"]) - int(t["Start_Timestamp"]),
+                 int(t["Grid_Size_X"]) // max(1, int(t["Workgroup_Size_X"]))))
+    lines += ["", f"{'kernel':<34}{'grids':>7}{'mean_us':>10}{'mean_wgs':>10}"]
+    for k in sorted(per_kernel, key=lambda k: -sum(d for d, _ in per_kernel[k])):
+        v = per_kernel[k]
+        lines.append(f"{k:<34}{len(v):>7}{sum(d for d, _ in v) / len(v) / 1e3:>10.1f}"
+                     f"{sum(g for _, g in v) / len(v):>10.0f}")
+        res[k] = {"grids": len(v), "mean_us": round(sum(d for d, _ in v) / len(v) / 1e3, 1)}
+    with open(os.path.join(out_dir, "zp_group_served_poisson_x4000_kernel_stats.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return res
+
+
 P29_PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_p29 -o run -- "
                    "python -u bench.py --p29-profile")
 P29_ROLES = ("encode", "dd", "dp", "dq")
@@ -1279,6 +1377,10 @@ def main():
                     help="write the profiles/ summary of a --p29-profile run (no GPU needed)")
     ap.add_argument("--summarize-p29-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ HBM-byte summary of the two --p29-profile counter runs (no GPU needed)")
+    ap.add_argument("--serve-profile", type=int, metavar="RUNS",
+                    help="only the saturated served stream, RUNS replays after a warm-up (for the profiler)")
+    ap.add_argument("--summarize-serve", metavar="STATS_DIR",
+                    help="write the profiles/ summary of a --serve-profile run (no GPU needed)")
     ap.add_argument("--config", type=int, choices=(1, 2, 3, 4, 5),
                     help="measure one workload only and print its JSON object: 1 launch latency at p=5, "
                          "2 the headline step (no extras), 3 p=29 recovery by class, 4 the 20,000-stripe plan, "
@@ -1306,6 +1408,9 @@ def main():
     if args.summarize_p29:
         print(json.dumps(summarize_p29_profile(args.summarize_p29), indent=1))
         return
+    if args.summarize_serve:
+        print(json.dumps(summarize_serve_profile(args.summarize_serve), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (stripes are independent, "
               "so more GPUs would each take a share of the stripes, with no communication between them).",
@@ -1317,7 +1422,7 @@ def main():
     if args.config == 2:
         args.no_extras = True
     if not (args.no_cpu_baseline or args.plan_profile or args.p29_profile or args.rows_probe or
-            args.config not in (None, 2)):
+            args.serve_profile or args.config not in (None, 2)):
         log("cpu baseline: oracle on every core (worker processes, before the GPU is touched)")
         parallel = cpu_oracle_parallel(max(1.0, args.cpu_seconds / 8))
 
@@ -1348,6 +1453,9 @@ def main():
         from paper_cs_0611109_amd import autotune as at
         at.load_cache()
         print(json.dumps(rows_probe(stream)), flush=True)
+        return
+    if args.serve_profile:
+        print(json.dumps(serve_profile(args.serve_profile)), flush=True)
         return
     if args.config not in (None, 2):
         from paper_cs_0611109_amd import autotune as at
