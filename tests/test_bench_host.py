@@ -1,7 +1,7 @@
 """Host-side logic of bench.py, on the CPU: the one-GPU refusal, the lookup
-of measured HBM traffic in the committed table, and the turning of
-rocprofv3 counter readings into bytes (scaled by the plain copies of known
-size that the counter runs include)."""
+of measured HBM traffic in the committed table, the turning of rocprofv3
+counter readings into bytes (scaled by the plain copies of known size that
+the counter runs include), and the summary of a served kernel trace."""
 
 import csv
 import json
@@ -97,3 +97,31 @@ def test_counter_summary_scales_by_the_probe_copies(tmp_path):
     assert (tmp_path / "traffic.json").exists()
     text = (tmp_path / f"{bench.WORKLOAD_TAG}_kernel_stats.txt").read_text()
     assert "encode    zp_split_kernel<13, 2, 4, 4, false, 2>: 2 launches, avg 450000 ns" in text
+
+
+def test_served_trace_summary_splits_runs_and_measures_busy_time(tmp_path):
+    """A warm-up run and two timed runs of grids, separated by idle gaps:
+    the warm-up is left out, and the busy fraction counts overlapping grids
+    once."""
+    k37 = "void raid6c::(anonymous namespace)::zp_group_lat_kernel<37>(raid6c::GroupArgs)"
+    km = "void raid6c::(anonymous namespace)::zp_group_multi_kernel(raid6c::GroupArgs)"
+    rows = []
+
+    def grid(name, s, e, stream):
+        rows.append({"Kernel_Name": name, "Start_Timestamp": s, "End_Timestamp": e, "Stream_Id": stream,
+                     "Grid_Size_X": 256 * 100, "Workgroup_Size_X": 256})
+
+    grid(k37, 0, 50_000, 1)                                  # warm-up run
+    base = 10_000_000
+    grid(k37, base, base + 100_000, 1)                       # run 1: two overlapping grids, then a gap
+    grid(km, base + 50_000, base + 200_000, 2)
+    grid(km, base + 300_000, base + 400_000, 1)
+    base = 20_000_000
+    grid(km, base, base + 100_000, 3)                        # run 2: one grid
+    (tmp_path / "t").mkdir()
+    _write_csv(tmp_path / "t" / "run_kernel_trace.csv", rows)
+    res = bench.summarize_serve_profile(str(tmp_path / "t"), out_dir=str(tmp_path))
+    assert [r["grids"] for r in res["runs"]] == [3, 1]
+    assert res["runs"][0]["span_us"] == 400.0 and res["runs"][0]["busy_frac"] == 0.75
+    assert res["runs"][1]["busy_frac"] == 1.0
+    assert res["zp_group_multi_kernel"]["grids"] == 3 and res["zp_group_lat_kernel<37>"]["grids"] == 1
